@@ -1,0 +1,171 @@
+"""Pins of the DMM simulator: the paper's schedules under the 0-1 argument of the
+Lemma 1 / Theorem 2 proofs, the layout conversions against hand-worked
+fixtures, and the bank-conflict accounting on textbook access patterns."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_worked.json")))
+
+
+def test_conversions_golden(sim):
+    g = GOLDEN["rm_to_cm_2x4"]
+    assert sim.rm_to_cm(np.array(g["M"])).tolist() == g["CM"]
+    g = GOLDEN["cm_to_rm_2x4"]
+    assert sim.cm_to_rm(np.array(g["M"])).tolist() == g["RM"]
+
+
+def test_conversion_index_maps(sim):
+    """RM->CM sends row-major position p to (p mod w, p // w); CM->RM is its inverse."""
+    w, m = 8, 64
+    M = np.arange(w * m).reshape(w, m)
+    C = sim.rm_to_cm(M)
+    for p in range(w * m):
+        assert C[p % w, p // w] == p
+    assert np.array_equal(sim.cm_to_rm(C), M)
+
+
+@pytest.mark.parametrize("w,m", [(2, 4), (2, 8)])
+def test_lemma1_exhaustive_01(sim, w, m):
+    for M in sim.all_binary_matrices(w, m):
+        assert sim.is_row_major_sorted(sim.lemma1(M))
+
+
+@pytest.mark.parametrize("w,m,count", [(4, 16, 3000), (8, 64, 400)])
+def test_lemma1_random_01(sim, w, m, count):
+    for M in sim.random_binary_matrices(w, m, count, seed=w * m):
+        assert sim.is_row_major_sorted(sim.lemma1(M))
+
+
+def test_lemma1_descending(sim):
+    rng = np.random.default_rng(0)
+    M = rng.integers(0, 1000, size=(4, 16))
+    out = sim.lemma1(M, descending=True).reshape(-1)
+    assert np.array_equal(out, np.sort(M.reshape(-1))[::-1])
+
+
+def test_lemma1_parity_of_alternation_irrelevant(sim):
+    for M in sim.all_binary_matrices(2, 8):
+        assert sim.is_row_major_sorted(sim.lemma1(M, even_rows_ascending=False))
+
+
+def test_lemma1_needs_alternation(sim):
+    fails = sum(not sim.is_row_major_sorted(sim.lemma1(M, alternate=False))
+                for M in sim.all_binary_matrices(2, 8))
+    assert fails > 0
+
+
+def test_lemma1_needs_two_repetitions(sim):
+    fails = sum(not sim.is_row_major_sorted(sim.lemma1(M, repetitions=1))
+                for M in sim.random_binary_matrices(4, 16, 3000, seed=1))
+    assert fails > 0
+
+
+def test_lemma1_needs_w_le_sqrt_m(sim):
+    fails = sum(not sim.is_row_major_sorted(sim.lemma1(M))
+                for M in sim.random_binary_matrices(16, 16, 300, seed=2))
+    assert fails > 0
+
+
+@pytest.mark.slow
+def test_theorem2_exhaustive_01_4x4(sim):
+    for M in sim.all_binary_matrices(4, 4):
+        assert sim.is_row_major_sorted(sim.theorem2(M, s=2))
+
+
+@pytest.mark.parametrize("w,m,s,count", [(16, 16, 4, 400), (64, 64, 8, 60),
+                                         (64, 128, 8, 30), (64, 256, 8, 15), (16, 32, 4, 400)])
+def test_theorem2_random_01(sim, w, m, s, count):
+    for M in sim.random_binary_matrices(w, m, count, seed=w + m + s):
+        assert sim.is_row_major_sorted(sim.theorem2(M, s=s))
+
+
+def test_theorem2_sorts_integers_like_numpy(sim):
+    rng = np.random.default_rng(4)
+    M = rng.integers(0, 2**32, size=(64, 64), dtype=np.int64)
+    assert np.array_equal(sim.theorem2(M).reshape(-1), np.sort(M.reshape(-1)))
+    L = rng.integers(0, 64, size=(64, 128))
+    assert np.array_equal(sim.theorem2(L, s=8).reshape(-1), np.sort(L.reshape(-1)))
+
+
+# -------------------------------------------------------------------------- conflict counter
+
+
+def test_conflicts_linear_and_strided(sim):
+    m64 = sim.BankModel(banks=64, phase_lanes=64, width=1)
+    lin = [(l, l) for l in range(64)]
+    assert sim.step_conflicts(lin, m64) == 0
+    strided = [(l, 64 * l) for l in range(64)]
+    assert sim.step_conflicts(strided, m64) == 63
+    # strided access A[w*i + t] of the Dotsenko layout: lane t only ever touches bank t
+    for i in range(5):
+        assert sim.step_conflicts([(t, 64 * i + t) for t in range(64)], m64) == 0
+
+
+def test_conflicts_broadcast_modes(sim):
+    m = sim.BankModel(64, 64, 1)
+    same = [(l, 17) for l in range(64)]
+    assert sim.step_conflicts(same, m, mode="hardware", is_read=True) == 0
+    assert sim.step_conflicts(same, m, mode="dmm") == 63
+
+
+def test_conflicts_padding_coprime(sim):
+    """Contiguous access with row length coprime to the bank count is conflict-free."""
+    m = sim.BankModel(64, 64, 1)
+    for L in (63, 65, 129):
+        assert sim.step_conflicts([(t, t * L + 3) for t in range(64)], m) == 0
+    assert sim.step_conflicts([(t, t * 64 + 3) for t in range(64)], m) == 63
+
+
+# ------------------------------------------------------ alternating-direction split (design)
+
+
+MODELS = [sim_model for sim_model in [
+    (64, 64, 1), (32, 32, 1), (64, 32, 2), (32, 16, 2), (64, 16, 4)]]
+
+
+@pytest.mark.parametrize("banks,phase,width", MODELS)
+def test_binary_split_writes_conflict_free(sim, banks, phase, width):
+    """Zeros fill a segment from the front, ones from the back: every 64-item column's
+    64 destinations are 64 cyclically consecutive slots, hence conflict-free."""
+    model = sim.BankModel(banks, phase, width)
+    rng = np.random.default_rng(banks + phase + width)
+    for trial in range(40):
+        size = 64 * int(rng.integers(1, 9))
+        base = 64 * int(rng.integers(0, 4))
+        bits = (rng.random(size) < rng.random()).astype(int)
+        dest, _ = sim.binary_split_positions(bits, base, size)
+        for k in range(size // 64):
+            acc = [(l, width * int(dest[64 * k + l])) for l in range(64)]
+            assert sim.step_conflicts(acc, model, is_read=False) == 0
+
+
+@pytest.mark.parametrize("banks,phase,width", MODELS)
+def test_binary_split_virtual_reads_conflict_free(sim, banks, phase, width):
+    model = sim.BankModel(banks, phase, width)
+    rng = np.random.default_rng(7)
+    for trial in range(40):
+        size = 64 * int(rng.integers(1, 9))
+        zeros = int(rng.integers(0, size + 1))
+        phys = sim.split_virtual_order(0, size, zeros)
+        for k in range(size // 64):
+            acc = [(l, width * int(phys[64 * k + l])) for l in range(64)]
+            assert sim.step_conflicts(acc, model, is_read=True) == 0
+
+
+def test_binary_split_lsd_is_a_stable_partition(sim):
+    """Repeated splits on label bits 0..5, each reading the previous result in its virtual
+    order, give the stable partition (compared with numpy's stable argsort)."""
+    rng = np.random.default_rng(8)
+    n = 4096
+    labels = rng.integers(0, 64, size=n)
+    order = np.arange(n)              # virtual order -> item id
+    for b in range(6):
+        bits = (labels[order] >> b) & 1
+        dest, zeros = sim.binary_split_positions(bits, 0, n)
+        phys = np.empty(n, dtype=np.int64)
+        phys[dest] = order            # physical array after the split
+        order = phys[sim.split_virtual_order(0, n, zeros)]
+    assert np.array_equal(order, np.argsort(labels, kind="stable"))
