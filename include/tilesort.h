@@ -1,0 +1,190 @@
+/*
+ * tilesort.h -- C interface of libtilesort.so: sorting, w-way partitioning
+ * and permuting tiles of 32-bit items in one workgroup's LDS on MI355X
+ * (gfx950) without LDS bank conflicts.
+ *
+ * The three problems are those of Afshani & Sitchinava, "Sorting and
+ * Permuting without Bank Conflicts on GPUs", Sec. 1 ("Problems of interest"):
+ * sorting, w-way partition (the abstract defines it as sorting an input with
+ * n/w copies of every label) and permutation.  Shared memory is the paper's
+ * w x m matrix with one row per bank (Sec. 1, "Model of Computation"); here
+ * w = 64 lanes of a wavefront and the LDS banks of one CU.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - All array pointers are DEVICE pointers (hipMalloc / torch allocations);
+ *    the caller owns every buffer.  The library allocates nothing on these
+ *    calls; the only scratch it uses is the caller's `workspace`.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call only enqueues work on that stream and returns; results are
+ *    ready when the stream is.
+ *  - Tiles: tile t is the item range [tile_offsets[t], tile_offsets[t+1]) of
+ *    the flat arrays.  `tile_offsets` is a device int64 array of num_tiles+1
+ *    non-decreasing entries, tile_offsets[0] >= 0.  `max_tile_len` is a host
+ *    upper bound on every tile's length (used to pick kernels); a longer tile
+ *    is skipped and flagged in the workspace error word (see ts_check).
+ *  - Keys / labels / permutation entries are contiguous 32-bit arrays indexed
+ *    by the global item index g.
+ *  - Payload: `channels` 32-bit words per item; word (g, c) lives at
+ *    payload[g * elem_stride + c * chan_stride] (units of 32-bit words).
+ *    Array-of-structs is elem_stride = channels, chan_stride = 1;
+ *    channel-planar is elem_stride = 1, chan_stride = total item count.
+ *    Any 32-bit type (fp32, int32, uint32) is moved bit-exactly.
+ *  - perm_out / pi are tile-local int32 indices.
+ *  - Input and output arrays must not overlap.
+ *  - Workspace: at least ts_workspace_bytes(...) bytes of device memory,
+ *    prepared once with ts_workspace_init.  It holds the error word and,
+ *    for some schedules, work-queue counters.  Calls that share a workspace
+ *    must be ordered on one stream.
+ *
+ * Errors: host-detectable argument problems return TS_ERR_INVALID (or
+ * TS_ERR_UNSUPPORTED for combinations not implemented) and set the message
+ * returned by ts_last_error() (thread-local).  A failed kernel launch returns
+ * TS_ERR_HIP.  Inputs that break the data contract (label >= num_classes,
+ * pi not a permutation of its tile) never cause out-of-bounds accesses --
+ * indices are masked to the tile -- but the output is unspecified; with
+ * TS_FLAG_VALIDATE the kernels record such inputs in the workspace error word
+ * and ts_check reports them.
+ */
+#ifndef TILESORT_H
+#define TILESORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ts_status {
+    TS_OK = 0,
+    TS_ERR_INVALID = 1,
+    TS_ERR_UNSUPPORTED = 2,
+    TS_ERR_HIP = 3,
+    TS_ERR_WORKSPACE = 4
+} ts_status;
+
+/* tile_permute directions */
+enum { TS_SCATTER = 0, /* out[pi[i]] = in[i] */
+       TS_GATHER = 1   /* out[i] = in[pi[i]] */ };
+
+/* flags */
+enum {
+    /* keys are IEEE binary32 bit patterns: compared through the order-preserving
+       map (negatives: all bits flipped; non-negatives: sign bit set), so -0 < +0;
+       the original bits are written to keys_out */
+    TS_FLAG_F32_ORDERED = 1u,
+    /* kernels check labels / pi against the data contract and record violations */
+    TS_FLAG_VALIDATE = 2u
+};
+
+/* Schedule selection, stored in flags bits 8..11 (TS_SCHED(x) = x << 8). */
+#define TS_SCHED(x) ((uint32_t)(x) << 8)
+enum {
+    TS_SCHED_AUTO = 0,    /* the plan chosen by the autotuner's table (default) */
+    TS_SCHED_SPLIT = 1,   /* alternating-direction binary splits (partition, permute, sort) */
+    TS_SCHED_THM2 = 2,    /* the paper's Theorem 2 schedule: Lemma 1 on super-rows,
+                             column sorts, row sorts (sort and partition) */
+    TS_SCHED_BITONIC = 3, /* register row sorts + conflict-free transposes (sort) */
+    TS_SCHED_NAIVE = 15   /* baseline: plain LDS counting / direct scatter, with bank
+                             conflicts (all three ops) */
+};
+
+/* Operation ids for ts_workspace_bytes */
+enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2 };
+
+/*
+ * tile_sort -- sorting (Sec. 1, "Problems of interest": sorting; Sec. 2, Lemma 1
+ * and Theorem 2).  Every tile is sorted ascending by its uint32 key; equal keys
+ * keep input order (stable), so the result is unique.
+ *   keys_in / keys_out  : uint32 [N]; keys_out receives the sorted original bits.
+ *   payload_in / out    : optional (channels may be 0; pointers may then be NULL);
+ *                         payload_out[k] = payload_in[source of k].
+ *   perm_out            : optional int32 [N]: tile-local source index of slot k.
+ * Supported tile length: max_tile_len <= 16384 for the single-tile schedules;
+ * longer tiles return TS_ERR_UNSUPPORTED.
+ */
+ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out,
+                    const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
+                    int64_t elem_stride, int64_t chan_stride, int32_t* perm_out,
+                    const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
+                    uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * tile_partition -- w-way partition (Sec. 1: an item with label i is sent to row i;
+ * abstract: partitioning = sorting an input with n/w copies of each label;
+ * Corollary 1 and Theorem 2 solve it in O(m) steps).  Labels are uint32 in
+ * [0, num_classes), 1 <= num_classes <= 64.  Output: items grouped by label in
+ * ascending label order, input order kept within a label (stable); labels_out,
+ * payload_out and perm_out (optional) follow that order.
+ */
+ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
+                         const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
+                         int64_t elem_stride, int64_t chan_stride, uint32_t num_classes,
+                         int32_t* perm_out,
+                         const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
+                         uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * tile_permute -- permutation (Sec. 1: an item labelled (i, j) goes to slot j of
+ * row i; here the label is the tile-local linear destination).  pi is int32 [N],
+ * a permutation of [0, len) inside every tile.
+ *   TS_SCATTER: out[pi[i]] = in[i];   TS_GATHER: out[i] = in[pi[i]].
+ * in / out use the payload addressing above with `channels` words per item.
+ * Supported tile length: max_tile_len <= 16384.
+ */
+ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels,
+                       int64_t elem_stride, int64_t chan_stride,
+                       const int32_t* pi, uint32_t direction,
+                       const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
+                       uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Bytes of workspace the given call needs (never 0). */
+size_t ts_workspace_bytes(int op, int64_t num_tiles, int64_t max_tile_len, uint32_t channels);
+
+/* Zero a workspace (its error word and counters) on `stream`.  Call once after
+   allocating it. */
+ts_status ts_workspace_init(void* workspace, size_t workspace_bytes, void* stream);
+
+/* Synchronise `stream`, read and clear the workspace error word.  Returns TS_OK,
+   or TS_ERR_INVALID with ts_last_error() describing the recorded violation. */
+ts_status ts_check(void* workspace, void* stream);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* ts_last_error(void);
+
+/* Library version string. */
+const char* ts_version(void);
+
+/* ------------------------------------------------------------------------------
+ * Measurement helpers (not part of the hot path).
+ * ------------------------------------------------------------------------------ */
+
+/* Plain device-to-device copy of `bytes` bytes with 16-byte vector loads/stores:
+   the HBM bandwidth reference kernel. */
+ts_status ts_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+/*
+ * LDS access probe.  One kernel launch = `waves` wavefronts per workgroup x
+ * `groups` workgroups; every wave repeats `iters` times one LDS instruction whose
+ * 64 per-lane addresses come from lane_words[64] (32-bit word index into a 64 KiB
+ * LDS array, taken modulo 16384 and rounded down to the access width).
+ *   op 0 = ds_read, 1 = ds_write, 2 = ds_bpermute (lane_words = source lane);
+ *   width = 1, 2 or 4 words (b32 / b64 / b128; bpermute: 1).
+ * cycles_out (device, one uint64 per wave) receives the s_memtime ticks of the
+ * timed loop; sink (device, 64 words per wave) receives data so the loop is kept.
+ */
+ts_status ts_lds_probe(const uint32_t* lane_words, int op, int width, int iters, int waves,
+                       int groups, uint64_t* cycles_out, uint32_t* sink, void* stream);
+
+/* Override a tuning knob of the kernel-selection table (used by the autotuner).
+   Knobs: "partition_waves_4096" (1, 2, 4, 8 or 16 waves per workgroup; 104 and 108:
+   4 or 8 waves with registers capped so four workgroups fit on a CU).
+   Returns TS_ERR_INVALID for an unknown knob or value. */
+ts_status ts_tune(const char* knob, int value);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TILESORT_H */

@@ -1,0 +1,267 @@
+// C interface of libtilesort.so: argument checks, kernel selection and error
+// reporting.  The declarations and their documentation are in include/tilesort.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "../../include/tilesort.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ts_status fail(ts_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+ts_status fail(ts_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+ts_status hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return TS_OK;
+    return fail(TS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Workspace layout: word 0 = error bits; words 1..63 reserved (counters); 256 bytes total.
+constexpr size_t kWorkspaceBytes = 256;
+
+int sched_of(uint32_t flags) { return (int)((flags >> 8) & 0xFu); }
+
+int bits_for(uint32_t classes) {
+    int b = 0;
+    while ((1u << b) < classes) ++b;
+    return b;
+}
+
+ts_status check_common(const int64_t* offsets, int64_t num_tiles, int64_t max_len,
+                       void* workspace, size_t ws_bytes) {
+    if (num_tiles < 0) return fail(TS_ERR_INVALID, "num_tiles < 0");
+    if (num_tiles > 0 && offsets == nullptr) return fail(TS_ERR_INVALID, "tile_offsets is NULL");
+    if (max_len < 0) return fail(TS_ERR_INVALID, "max_tile_len < 0");
+    if (workspace == nullptr) return fail(TS_ERR_WORKSPACE, "workspace is NULL");
+    if (ws_bytes < kWorkspaceBytes)
+        return fail(TS_ERR_WORKSPACE, "workspace too small (%zu < %zu bytes)", ws_bytes, kWorkspaceBytes);
+    return TS_OK;
+}
+
+ts_status check_payload(const uint32_t* in, const uint32_t* out, uint32_t channels, int64_t es,
+                        int64_t cs, bool need_out) {
+    if (channels == 0) return TS_OK;
+    if (in == nullptr) return fail(TS_ERR_INVALID, "payload_in is NULL with channels > 0");
+    if (need_out && out == nullptr) return fail(TS_ERR_INVALID, "payload_out is NULL with channels > 0");
+    if (es < 0 || cs < 0) return fail(TS_ERR_INVALID, "negative payload stride");
+    if (channels > 1 && cs == 0) return fail(TS_ERR_INVALID, "chan_stride == 0 with channels > 1");
+    if (in == out) return fail(TS_ERR_INVALID, "payload_in and payload_out alias");
+    return TS_OK;
+}
+
+}  // namespace
+
+namespace ts {
+
+int num_cus() {
+    static int cus = [] {
+        int dev = 0, v = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        return v;
+    }();
+    return cus;
+}
+
+int persistent_grid(const void* kernel, int block_threads, size_t dyn_lds, int64_t work) {
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> cache;
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(kernel);
+        if (it == cache.end()) {
+            int b = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, block_threads, dyn_lds) != hipSuccess || b <= 0)
+                b = 1;
+            cache[kernel] = b;
+            per_cu = b;
+        } else {
+            per_cu = it->second;
+        }
+    }
+    int64_t g = (int64_t)per_cu * num_cus();
+    if (work < g) g = work;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace ts
+
+extern "C" {
+
+const char* ts_last_error(void) { return g_last_error.c_str(); }
+
+const char* ts_version(void) { return "tilesort 0.1 (gfx950)"; }
+
+size_t ts_workspace_bytes(int op, int64_t num_tiles, int64_t max_tile_len, uint32_t channels) {
+    (void)op;
+    (void)num_tiles;
+    (void)max_tile_len;
+    (void)channels;
+    return kWorkspaceBytes;
+}
+
+ts_status ts_workspace_init(void* workspace, size_t workspace_bytes, void* stream) {
+    if (workspace == nullptr) return fail(TS_ERR_WORKSPACE, "workspace is NULL");
+    return hip_status(ts::launch_fill_zero(workspace, workspace_bytes, (hipStream_t)stream),
+                      "workspace init");
+}
+
+ts_status ts_check(void* workspace, void* stream) {
+    if (workspace == nullptr) return fail(TS_ERR_WORKSPACE, "workspace is NULL");
+    uint32_t word = 0;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(&word, workspace, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, "ts_check");
+    if (word == 0) return TS_OK;
+    e = ts::launch_fill_zero(workspace, 4, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    std::string msg;
+    if (word & ts::ERR_TILE_TOO_LONG) msg += "a tile was longer than the kernel capacity (skipped); ";
+    if (word & ts::ERR_BAD_LABEL) msg += "label >= num_classes; ";
+    if (word & ts::ERR_BAD_PERM) msg += "pi is not a permutation of its tile; ";
+    return fail(TS_ERR_INVALID, "device reported: %s", msg.c_str());
+}
+
+ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
+                         const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
+                         int64_t elem_stride, int64_t chan_stride, uint32_t num_classes,
+                         int32_t* perm_out, const int64_t* tile_offsets, int64_t num_tiles,
+                         int64_t max_tile_len, uint32_t flags, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+    ts_status st = check_common(tile_offsets, num_tiles, max_tile_len, workspace, workspace_bytes);
+    if (st != TS_OK) return st;
+    if (num_classes < 1 || num_classes > 64)
+        return fail(TS_ERR_INVALID, "num_classes must be in [1, 64] (got %u)", num_classes);
+    if (num_tiles > 0 && labels_in == nullptr) return fail(TS_ERR_INVALID, "labels_in is NULL");
+    if (labels_in != nullptr && labels_in == labels_out)
+        return fail(TS_ERR_INVALID, "labels_in and labels_out alias");
+    st = check_payload(payload_in, payload_out, channels, elem_stride, chan_stride, true);
+    if (st != TS_OK) return st;
+    if (channels > 1)
+        return fail(TS_ERR_UNSUPPORTED, "tile_partition: channels > 1 not supported (got %u)", channels);
+    if (max_tile_len > ts::partition_split_capacity())
+        return fail(TS_ERR_UNSUPPORTED, "tile_partition: max_tile_len %lld > %lld",
+                    (long long)max_tile_len, (long long)ts::partition_split_capacity());
+    ts::PartitionArgs a{};
+    a.labels_in = labels_in;
+    a.labels_out = labels_out;
+    a.pay = ts::PayloadRef{payload_in, payload_out, channels, elem_stride, chan_stride};
+    a.perm_out = perm_out;
+    a.offsets = tile_offsets;
+    a.num_tiles = num_tiles;
+    a.num_classes = num_classes;
+    a.nbits = bits_for(num_classes);
+    a.validate = (flags & TS_FLAG_VALIDATE) ? 1u : 0u;
+    a.err = (uint32_t*)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    const int sched = sched_of(flags);
+    hipError_t e;
+    switch (sched) {
+        case TS_SCHED_AUTO:
+        case TS_SCHED_SPLIT: e = ts::launch_partition_split(a, max_tile_len, s); break;
+        case TS_SCHED_NAIVE: e = ts::launch_partition_naive(a, max_tile_len, s); break;
+        default: return fail(TS_ERR_UNSUPPORTED, "tile_partition: schedule %d not available", sched);
+    }
+    return hip_status(e, "tile_partition launch");
+}
+
+ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int64_t elem_stride,
+                       int64_t chan_stride, const int32_t* pi, uint32_t direction,
+                       const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
+                       uint32_t flags, void* workspace, size_t workspace_bytes, void* stream) {
+    ts_status st = check_common(tile_offsets, num_tiles, max_tile_len, workspace, workspace_bytes);
+    if (st != TS_OK) return st;
+    if (direction != TS_SCATTER && direction != TS_GATHER)
+        return fail(TS_ERR_INVALID, "tile_permute: direction must be TS_SCATTER or TS_GATHER");
+    if (num_tiles > 0 && pi == nullptr) return fail(TS_ERR_INVALID, "tile_permute: pi is NULL");
+    if (channels == 0) return TS_OK;
+    if (in == nullptr || out == nullptr) return fail(TS_ERR_INVALID, "tile_permute: in/out is NULL");
+    st = check_payload(in, out, channels, elem_stride, chan_stride, true);
+    if (st != TS_OK) return st;
+    if (max_tile_len > ts::permute_split_capacity())
+        return fail(TS_ERR_UNSUPPORTED, "tile_permute: max_tile_len %lld > %lld",
+                    (long long)max_tile_len, (long long)ts::permute_split_capacity());
+    ts::PermuteArgs a{};
+    a.pay = ts::PayloadRef{in, out, channels, elem_stride, chan_stride};
+    a.pi = pi;
+    a.direction = direction;
+    a.offsets = tile_offsets;
+    a.num_tiles = num_tiles;
+    a.validate = (flags & TS_FLAG_VALIDATE) ? 1u : 0u;
+    a.err = (uint32_t*)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    const int sched = sched_of(flags);
+    hipError_t e;
+    switch (sched) {
+        case TS_SCHED_AUTO:
+        case TS_SCHED_SPLIT: e = ts::launch_permute_split(a, max_tile_len, s); break;
+        case TS_SCHED_NAIVE: e = ts::launch_permute_naive(a, max_tile_len, s); break;
+        default: return fail(TS_ERR_UNSUPPORTED, "tile_permute: schedule %d not available", sched);
+    }
+    return hip_status(e, "tile_permute launch");
+}
+
+ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* payload_in,
+                    uint32_t* payload_out, uint32_t channels, int64_t elem_stride,
+                    int64_t chan_stride, int32_t* perm_out, const int64_t* tile_offsets,
+                    int64_t num_tiles, int64_t max_tile_len, uint32_t flags, void* workspace,
+                    size_t workspace_bytes, void* stream) {
+    (void)keys_in; (void)keys_out; (void)payload_in; (void)payload_out; (void)channels;
+    (void)elem_stride; (void)chan_stride; (void)perm_out; (void)tile_offsets; (void)num_tiles;
+    (void)max_tile_len; (void)flags; (void)workspace; (void)workspace_bytes; (void)stream;
+    return fail(TS_ERR_UNSUPPORTED, "tile_sort: not built yet");
+}
+
+ts_status ts_tune(const char* knob, int value) {
+    if (knob == nullptr) return fail(TS_ERR_INVALID, "ts_tune: knob is NULL");
+    if (std::strcmp(knob, "partition_waves_4096") == 0) {
+        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16 && value != 104 &&
+            value != 108)
+            return fail(TS_ERR_INVALID, "ts_tune: partition_waves_4096 must be 1, 2, 4, 8, 16, 104 or 108");
+        ts::set_partition_waves(value);
+        return TS_OK;
+    }
+    return fail(TS_ERR_INVALID, "ts_tune: unknown knob '%s'", knob);
+}
+
+ts_status ts_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (bytes == 0) return TS_OK;
+    if (src == nullptr || dst == nullptr) return fail(TS_ERR_INVALID, "ts_copy: NULL pointer");
+    return hip_status(ts::launch_copy(src, dst, bytes, (hipStream_t)stream), "ts_copy launch");
+}
+
+ts_status ts_lds_probe(const uint32_t* lane_words, int op, int width, int iters, int waves,
+                       int groups, uint64_t* cycles_out, uint32_t* sink, void* stream) {
+    if (lane_words == nullptr || cycles_out == nullptr || sink == nullptr)
+        return fail(TS_ERR_INVALID, "ts_lds_probe: NULL pointer");
+    if (op < 0 || op > 2) return fail(TS_ERR_INVALID, "ts_lds_probe: op must be 0, 1 or 2");
+    if (!(width == 1 || width == 2 || width == 4) || (op == 2 && width != 1))
+        return fail(TS_ERR_INVALID, "ts_lds_probe: bad width");
+    if (iters < 1 || waves < 1 || waves > 16 || groups < 1)
+        return fail(TS_ERR_INVALID, "ts_lds_probe: bad iters/waves/groups");
+    return hip_status(ts::launch_lds_probe(lane_words, op, width, iters, waves, groups, cycles_out,
+                                           sink, (hipStream_t)stream),
+                      "ts_lds_probe launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Device helpers shared by the tile kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+#define TS_DEV __device__ __forceinline__
+
+namespace ts {
+
+constexpr int WAVE = 64;
+
+TS_DEV int lane_id() {
+    return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+TS_DEV uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Number of set bits of `mask` in lanes below the calling lane.
+TS_DEV uint32_t count_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Same, plus an addend (folded into the mbcnt accumulator).
+TS_DEV uint32_t count_below_plus(uint64_t mask, uint32_t add) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, add));
+}
+
+TS_DEV int popc64(uint64_t m) { return __popcll(m); }
+
+// Make the compiler treat v as changed here, so values derived from it are computed
+// inside the enclosing loop instead of being hoisted and kept live in registers.
+TS_DEV uint32_t opaque(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Per-lane select driven by a wave mask (e.g. a ballot): lane bit set -> if1, else if0.
+// One v_cndmask with the mask as its SGPR-pair condition.
+TS_DEV uint32_t select_by_mask(uint64_t mask, uint32_t if0, uint32_t if1) {
+    uint32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if0), "v"(if1), "s"(mask));
+    return r;
+}
+
+// Issue CPW coalesced 32-bit global loads of one tile, column j = items 64*(c0+j) + lane,
+// with no waits between them: lanes past the end of the tile read item 0 instead (valid
+// for n > 0) and the caller replaces those values.  Element g of the tile is at
+// base[(o + g) * stride].  Unit stride uses a wave-uniform tile pointer and 32-bit lane
+// offsets (scalar-base addressing); other strides use 64-bit addresses.
+template <int CPW, typename T>
+TS_DEV void load_columns(const T* __restrict__ base, int64_t stride, int64_t o, int n, int c0,
+                         int lane, T (&out)[CPW]) {
+    if (stride == 1) {
+        // 32-bit byte offsets from a uniform pointer: scalar-base (saddr) global loads
+        const char* tb = (const char*)(base + o);
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const uint32_t i = (uint32_t)(64 * (c0 + j) + lane);
+            const uint32_t off = ((i < (uint32_t)n) ? i : 0u) * (uint32_t)sizeof(T);
+            out[j] = *(const T*)(tb + off);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const int i = 64 * (c0 + j) + lane;
+            const int ii = (i < n) ? i : 0;
+            out[j] = base[(o + ii) * stride];
+        }
+    }
+}
+
+// Store element g = 64*c + lane of a tile (g < n) at base[(o + g) * stride].
+template <typename T>
+TS_DEV void store_item(T* __restrict__ base, int64_t stride, int64_t o, int g, T v) {
+    if (stride == 1) *(T*)((char*)(base + o) + (uint32_t)g * (uint32_t)sizeof(T)) = v;
+    else base[(o + g) * stride] = v;
+}
+
+// LDS accesses at a byte offset from the start of an LDS array.
+template <typename T>
+TS_DEV T lds_load(const T* base, uint32_t byte_off) {
+    return *(const T*)((const char*)base + byte_off);
+}
+template <typename T>
+TS_DEV void lds_store(T* base, uint32_t byte_off, T v) {
+    *(T*)((char*)base + byte_off) = v;
+}
+
+TS_DEV uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+TS_DEV uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+TS_DEV uint64_t pack(uint32_t hi, uint32_t lo) { return ((uint64_t)hi << 32) | lo; }
+
+// Order-preserving map of binary32 bit patterns to uint32 (and back).
+TS_DEV uint32_t f32_to_ordered(uint32_t b) {
+    uint32_t flip = (uint32_t)((int32_t)b >> 31) | 0x80000000u;
+    return b ^ flip;
+}
+TS_DEV uint32_t ordered_to_f32(uint32_t u) {
+    uint32_t flip = ((u >> 31) - 1u) | 0x80000000u;
+    return u ^ flip;
+}
+
+// Record an error bit once per wave.
+TS_DEV void flag_error(uint32_t* err, bool bad, uint32_t bit) {
+    uint64_t any = ballot(bad);
+    if (any != 0 && lane_id() == (int)(__builtin_ctzll(any))) atomicOr(err, bit);
+}
+
+}  // namespace ts

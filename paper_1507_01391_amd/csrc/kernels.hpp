@@ -1,0 +1,83 @@
+// Internal launch interface between the C ABI layer (api.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ts {
+
+// Bits of the workspace error word.
+enum : uint32_t {
+    ERR_TILE_TOO_LONG = 1u,   // a tile exceeded the kernel's capacity and was skipped
+    ERR_BAD_LABEL = 2u,       // TS_FLAG_VALIDATE: label >= num_classes
+    ERR_BAD_PERM = 4u,        // TS_FLAG_VALIDATE: pi is not a permutation of its tile
+};
+
+
+struct PayloadRef {
+    const uint32_t* in;
+    uint32_t* out;
+    uint32_t channels;
+    int64_t es;  // element stride (words)
+    int64_t cs;  // channel stride (words)
+};
+
+struct PartitionArgs {
+    const uint32_t* labels_in;
+    uint32_t* labels_out;
+    PayloadRef pay;
+    int32_t* perm_out;
+    const int64_t* offsets;
+    int64_t num_tiles;
+    uint32_t num_classes;
+    int nbits;          // ceil(log2(num_classes))
+    uint32_t validate;  // nonzero: check labels
+    uint32_t* err;      // workspace error word
+};
+
+struct PermuteArgs {
+    PayloadRef pay;     // in / out with channels and strides
+    const int32_t* pi;
+    uint32_t direction;
+    const int64_t* offsets;
+    int64_t num_tiles;
+    uint32_t validate;
+    uint32_t* err;
+};
+
+struct SortArgs {
+    const uint32_t* keys_in;
+    uint32_t* keys_out;
+    PayloadRef pay;
+    int32_t* perm_out;
+    const int64_t* offsets;
+    int64_t num_tiles;
+    uint32_t f32;       // nonzero: keys are binary32 patterns
+    uint32_t* err;
+};
+
+// Device properties cached by the API layer.
+int num_cus();
+
+// Each returns hipSuccess or the launch error.  `cap` is the kernel's tile capacity.
+hipError_t launch_partition_split(const PartitionArgs& a, int64_t max_len, hipStream_t s);
+hipError_t launch_partition_naive(const PartitionArgs& a, int64_t max_len, hipStream_t s);
+hipError_t launch_partition_thm2(const PartitionArgs& a, int64_t max_len, hipStream_t s);
+hipError_t launch_permute_split(const PermuteArgs& a, int64_t max_len, hipStream_t s);
+hipError_t launch_permute_naive(const PermuteArgs& a, int64_t max_len, hipStream_t s);
+hipError_t launch_sort(const SortArgs& a, int64_t max_len, int sched, hipStream_t s);
+
+int64_t partition_split_capacity();
+void set_partition_waves(int nw);
+int64_t permute_split_capacity();
+int64_t sort_capacity(int sched);
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_lds_probe(const uint32_t* lane_words, int op, int width, int iters, int waves,
+                            int groups, uint64_t* cycles_out, uint32_t* sink, hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// Grid size for a persistent kernel: min(work items, resident blocks on the device).
+int persistent_grid(const void* kernel, int block_threads, size_t dyn_lds, int64_t work);
+
+}  // namespace ts

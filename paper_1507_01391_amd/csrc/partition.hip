@@ -1,0 +1,226 @@
+// Stable w-way partition of tiles held in LDS, without LDS bank conflicts.
+//
+// Problem: Afshani & Sitchinava, Sec. 1 ("Problems of interest", partition) and
+// the abstract (partitioning = sorting an input with n/w copies of each label).
+//
+// Schedule ("alternating-direction binary split"): one pass per label bit,
+// least significant first.  A pass reads the tile in its current order, 64
+// consecutive items per wave instruction ("column"), and writes the items whose
+// bit is 0 forward from the front of the tile and the items whose bit is 1
+// backward from the back.  After k columns the zero block ends at z and the one
+// block starts at N - (64k - z); both heads therefore sit on the same bank
+// residue (N is a multiple of 64), and the next column's zeros (forward from
+// that residue) and ones (backward from it) cover 64 cyclically consecutive
+// item slots: one per bank, i.e. every write instruction respects the paper's
+// Conflict Avoidance Condition (Sec. 1).  Reading the result zero block forward
+// and one block backward ("virtual order") restores input order inside each
+// half, so each pass is a stable split and nbits passes are an LSD radix sort on
+// the label -- the stable partition.  The virtual-order reads are conflict-free
+// for the same reason (a column meets the turning point at most once, and the
+// two pieces cover complementary residues).  The alternation of directions plays
+// the role of the "alternating order" rows of Lemma 1 (Sec. 2).
+//
+// Per tile: labels and one payload word are packed in a 64-bit item
+// (hi = source position << 16 | label, lo = payload) and live in registers
+// between passes; LDS holds one copy of the tile (8 bytes per item).  The next
+// tile's labels and payload are loaded into registers while the current tile is
+// being split, so HBM latency overlaps the LDS work.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ts {
+
+namespace {
+
+template <int CPW>
+struct TileLoad {
+    int64_t o;   // first item of the tile
+    int n;       // tile length (or -1 when there is no tile)
+    uint32_t lab[CPW];
+    uint32_t pay[CPW];
+};
+
+// Issue the global loads of one tile (no waits).  Lanes past the end read item 0 of
+// the tile (always valid when n > 0) and are replaced by padding later.
+template <int CPW, int CAP>
+TS_DEV void issue_tile_load(const PartitionArgs& a, const int64_t* __restrict__ offs, int64_t t,
+                            int w, int lane, TileLoad<CPW>& L) {
+    if (t >= a.num_tiles) {
+        L.n = -1;
+        return;
+    }
+    const int64_t o = offs[t];
+    const int64_t len = offs[t + 1] - o;
+    L.o = o;
+    L.n = (len > CAP) ? -2 : (int)len;
+    const bool has_pay = a.pay.channels > 0;
+    if (L.n <= 0) return;
+    load_columns<CPW>(a.labels_in, 1, o, L.n, w * CPW, lane, L.lab);
+    if (has_pay) load_columns<CPW>(a.pay.in, a.pay.es, o, L.n, w * CPW, lane, L.pay);
+}
+
+template <int NW, int CAP, int WPE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void partition_split_kernel(PartitionArgs a, const int64_t* __restrict__ offs) {
+    constexpr int CPW = CAP / 64 / NW;  // columns per wave
+    // Narrow waves have room to load the next tile during this one; wide ones load
+    // each tile when they start it.
+    constexpr bool PREFETCH = CPW <= 16 && WPE == 0;
+    __shared__ uint64_t A[CAP];
+    __shared__ int wz[NW];
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lmask = (1u << a.nbits) - 1u;
+    const bool has_pay = a.pay.channels > 0;
+
+    TileLoad<CPW> L;
+    int64_t t = blockIdx.x;
+    issue_tile_load<CPW, CAP>(a, offs, t, w, lane, L);
+
+    for (; t < a.num_tiles; t += gridDim.x) {
+        const int64_t o = L.o;
+        const int n = L.n;
+        if (n == -2) {  // longer than this kernel's capacity: skip and flag
+            if (threadIdx.x == 0) atomicOr(a.err, ERR_TILE_TOO_LONG);
+            if (PREFETCH) issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
+            else if (t + gridDim.x < a.num_tiles) issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
+            continue;
+        }
+        // The tile is padded to the kernel capacity: every wave always owns CPW full
+        // columns, so all loop bounds and branches below are wave-uniform constants.
+        constexpr int N = CAP;
+
+        // ---- items of this tile: column k, lane l holds item 64k + l.  Padding items
+        //      carry the largest label and a position >= n, so they end up last.
+        uint64_t e[CPW];
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const int i = 64 * (w * CPW + j) + lane;
+            uint32_t lab = lmask, pay = 0;
+            if (i < n) {
+                lab = L.lab[j];
+                bad |= lab >= a.num_classes;
+                lab &= lmask;
+                pay = L.pay[j];
+            }
+            e[j] = pack(((uint32_t)i << 16) | lab, pay);
+        }
+        if (a.validate) flag_error(a.err, bad, ERR_BAD_LABEL);
+
+        // ---- prefetch the next tile while this one is split in LDS
+        if (PREFETCH) issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
+
+        // ---- one stable split per label bit.  Addresses are byte offsets into A built from
+        //      one lane-dependent register plus wave-uniform scalars and the DS immediate
+        //      offset, so no per-column address registers stay live across passes.
+        const uint32_t lane8 = (uint32_t)lane * 8u;
+        const uint32_t neg_lane8 = 0u - lane8;
+        const uint32_t fwd_base = lane8 + (uint32_t)(w * CPW * 512);  // column j at + 512 j
+        for (int b = 0; b < a.nbits; ++b) {
+            // Zeros before this wave's first column (zb) and in the whole tile (zt).
+            constexpr bool KEEP = (NW > 1);  // ballots are kept between the two loops
+            uint64_t bal[KEEP ? CPW : 1];
+            int zb = 0, zt = 0;
+            if (KEEP) {
+                int zc = 0;
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) {
+                    bal[j] = ballot((hi32(e[j]) >> b) & 1u);
+                    zc += 64 - popc64(bal[j]);
+                }
+                if (lane == 0) wz[w] = zc;
+                __syncthreads();  // every wave has read the previous pass and posted its count
+                const int mine = (lane < NW) ? wz[lane] : 0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const int v = __builtin_amdgcn_readlane(mine, q);
+                    zt += v;
+                    zb += (q < w) ? v : 0;
+                }
+            }
+            // Write: zeros of column k go to z + rank0, ones to N-1-(ones before)-rank1.
+            int z = zb;  // zeros before the current column (whole tile, in order)
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int k = w * CPW + j;
+                const uint64_t bj = KEEP ? bal[KEEP ? j : 0] : ballot((hi32(e[j]) >> b) & 1u);
+                const uint32_t r0 = count_below(~bj);  // zeros in lower lanes
+                const uint32_t z8 = (uint32_t)__builtin_amdgcn_readfirstlane(z * 8);
+                const uint32_t o8 = (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 - 64 * k + z) * 8);
+                const uint32_t a0 = r0 * 8u + z8;                 // zero: z + rank0
+                const uint32_t a1 = (r0 * 8u + neg_lane8) + o8;   // one: N-1-(64k-z)-(lane-rank0)
+                lds_store(A, select_by_mask(bj, a0, a1), e[j]);
+                z += 64 - popc64(bj);
+            }
+            if (NW == 1) zt = z;
+            if (NW > 1) __syncthreads();  // the split tile is complete
+            // Read back in virtual order: zero block forward, then one block backward.
+            const uint32_t rev_base =
+                (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 + zt - 64 * w * CPW - 64 * (CPW - 1)) * 8) +
+                neg_lane8;  // column j (reversed) at + 512 (CPW-1-j)
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int base = 64 * (w * CPW + j);
+                if (base + 64 <= zt) {
+                    e[j] = lds_load(A, fwd_base + 512u * j);
+                } else if (base >= zt) {
+                    e[j] = lds_load(A, rev_base + 512u * (CPW - 1 - j));
+                } else {
+                    e[j] = lds_load(A, (lane < zt - base) ? fwd_base + 512u * j
+                                                          : rev_base + 512u * (CPW - 1 - j));
+                }
+            }
+        }
+
+        // ---- store in order (coalesced: column k covers items 64k .. 64k+63)
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const int v = 64 * (w * CPW + j) + lane;
+            if (v < n) {
+                const uint32_t h = hi32(e[j]);
+                if (a.labels_out) store_item(a.labels_out, 1, o, v, h & 0xFFFFu);
+                if (has_pay) store_item(a.pay.out, a.pay.es, o, v, lo32(e[j]));
+                if (a.perm_out) store_item(a.perm_out, 1, o, v, (int32_t)(h >> 16));
+            }
+        }
+        if (!PREFETCH) issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
+    }
+}
+
+template <int NW, int CAP, int WPE = 0>
+hipError_t launch_split(const PartitionArgs& a, hipStream_t s) {
+    auto kern = partition_split_kernel<NW, CAP, WPE>;
+    const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, a.offsets);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t partition_split_capacity() { return 16384; }
+
+// Wave count per workgroup for the 4096-item kernel (tuning knob, see the plan table).
+static int g_part_nw4096 = 8;
+void set_partition_waves(int nw) { g_part_nw4096 = nw; }
+
+hipError_t launch_partition_split(const PartitionArgs& a, int64_t max_len, hipStream_t s) {
+    if (a.num_tiles == 0) return hipSuccess;
+    if (max_len <= 1024) return launch_split<4, 1024>(a, s);
+    if (max_len <= 2048) return launch_split<4, 2048>(a, s);
+    if (max_len <= 4096) {
+        switch (g_part_nw4096) {
+            case 1: return launch_split<1, 4096>(a, s);
+            case 2: return launch_split<2, 4096>(a, s);
+            case 4: return launch_split<4, 4096>(a, s);
+            case 16: return launch_split<16, 4096>(a, s);
+            case 108: return launch_split<8, 4096, 8>(a, s);   // 8 waves, 4 workgroups per CU
+            case 104: return launch_split<4, 4096, 4>(a, s);   // 4 waves, 4 workgroups per CU
+            default: return launch_split<8, 4096>(a, s);
+        }
+    }
+    if (max_len <= 8192) return launch_split<8, 8192>(a, s);
+    return launch_split<16, 16384>(a, s);
+}
+
+}  // namespace ts

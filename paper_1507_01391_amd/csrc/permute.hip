@@ -1,0 +1,114 @@
+// Tile-local permutation without LDS bank conflicts (Afshani & Sitchinava, Sec. 1,
+// "Problems of interest", permutation).  The routing itself is in route.hpp.
+//
+//   SCATTER  out[pi[i]] = in[i]: item (in[i], destination pi[i]) is routed once.
+//   GATHER   out[i] = in[pi[i]]: first the index i is routed to slot pi[i], which
+//            leaves inv[q] (the output slot that wants in[q]) at every slot q; then
+//            (in[q], destination inv[q]) is routed.  The first routing is shared by
+//            all payload channels.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "route.hpp"
+
+namespace ts {
+
+namespace {
+
+template <int NW, int CAP, bool GATHER>
+__global__ __launch_bounds__(NW * 64) void permute_split_kernel(PermuteArgs a,
+                                                               const int64_t* __restrict__ offs) {
+    using R = Router<NW, CAP>;
+    constexpr int CPW = R::CPW;
+    __shared__ uint64_t A[CAP];
+    __shared__ int wz[NW];
+    const int lane0 = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    constexpr bool gather = GATHER;
+
+    for (int64_t t = blockIdx.x; t < a.num_tiles; t += gridDim.x) {
+        const int lane = (int)opaque((uint32_t)lane0);
+        const uint32_t own_base = (uint32_t)lane * 8u + (uint32_t)(w * CPW * 512);
+        const int64_t o = offs[t];
+        const int64_t len = offs[t + 1] - o;
+        if (len > CAP) {
+            if (threadIdx.x == 0) atomicOr(a.err, ERR_TILE_TOO_LONG);
+            continue;
+        }
+        const int n = (int)len;
+
+        // ---- destinations: item i (column k, lane l; i = 64k + l) goes to pi[i];
+        //      padding items i >= n keep their own index, so the destinations always
+        //      form a permutation of [0, CAP).
+        uint32_t dst[CPW];
+        bool bad = false;
+        int32_t piv[CPW];
+        if (n > 0) load_columns<CPW>(a.pi, 1, o, n, w * CPW, lane, piv);
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const int i = 64 * (w * CPW + j) + lane;
+            const int32_t q = piv[j];
+            bad |= (i < n) && (q < 0 || q >= n);
+            dst[j] = (i < n) ? ((uint32_t)q & (uint32_t)(CAP - 1)) : (uint32_t)i;
+        }
+        if (a.validate) flag_error(a.err, bad, ERR_BAD_PERM);
+
+        uint64_t e[CPW];
+        if (gather) {
+            // route the request index i to slot pi[i]: slot q then holds inv[q]
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int i = 64 * (w * CPW + j) + lane;
+                e[j] = pack(dst[j], (uint32_t)i);
+            }
+            R::route(A, wz, e, w, lane);
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const uint64_t x = lds_load(A, own_base + 512u * j);
+                if (a.validate) flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)(64 * (w * CPW + j) + lane), ERR_BAD_PERM);
+                dst[j] = lo32(x);  // inv[q] for q = 64k + l
+            }
+            __syncthreads();  // A is reused by the next routing
+        }
+
+#pragma unroll 1
+        for (uint32_t c = 0; c < a.pay.channels; ++c) {
+            const int64_t cbase = (int64_t)c * a.pay.cs;
+            uint32_t xv[CPW];
+            if (n > 0) load_columns<CPW>(a.pay.in + cbase, a.pay.es, o, n, w * CPW, lane, xv);
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) e[j] = pack(dst[j], xv[j]);
+            R::route(A, wz, e, w, lane);
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int v = 64 * (w * CPW + j) + lane;
+                const uint64_t x = lds_load(A, own_base + 512u * j);
+                if (a.validate && c == 0 && !gather)
+                    flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)v, ERR_BAD_PERM);
+                if (v < n) store_item(a.pay.out + cbase, a.pay.es, o, v, lo32(x));
+            }
+            __syncthreads();  // A is reused by the next channel / tile
+        }
+    }
+}
+
+template <int NW, int CAP>
+hipError_t launch_perm(const PermuteArgs& a, hipStream_t s) {
+    auto kern = (a.direction == 1) ? permute_split_kernel<NW, CAP, true>
+                                   : permute_split_kernel<NW, CAP, false>;
+    const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, a.offsets);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t permute_split_capacity() { return 16384; }
+
+hipError_t launch_permute_split(const PermuteArgs& a, int64_t max_len, hipStream_t s) {
+    if (a.num_tiles == 0) return hipSuccess;
+    if (max_len <= 4096) return launch_perm<8, 4096>(a, s);
+    if (max_len <= 8192) return launch_perm<16, 8192>(a, s);
+    return launch_perm<16, 16384>(a, s);
+}
+
+}  // namespace ts

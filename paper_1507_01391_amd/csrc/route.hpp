@@ -1,0 +1,110 @@
+// Conflict-free routing of a tile of 64-bit items to given destinations inside LDS.
+//
+// This is the permutation problem of Afshani & Sitchinava (Sec. 1, "Problems of
+// interest": an item labelled (i, j) goes to slot j of bank i), solved by
+// reducing it to a balanced w-way partition by destination bank followed by an
+// in-bank placement:
+//
+//  1. Six binary splits, most significant bank bit first.  At level L the tile is
+//     2^L equal segments; every segment sends the items whose next bank bit is 0
+//     forward from its front and those whose bit is 1 backward from its back.
+//     Because the destinations form a permutation, each half receives exactly
+//     half the items, so segment boundaries stay at fixed multiples of the
+//     column size, and every column's 64 writes land on 64 cyclically
+//     consecutive slots: one per bank, for any phase grouping (the same
+//     argument as the partition kernel's split).  Reads are linear.
+//  2. After the splits, group g (m = N/64 consecutive slots) holds exactly the m
+//     items bound for bank g.  In placement step t lane l reads item
+//     (t + l) mod m of group l (a skewed, conflict-free read) and writes it to
+//     its destination slot, which lies in bank l: every lane writes its own bank.
+//
+// Items carry the destination in the low 16 bits of their high word.  The tile
+// is padded to the capacity; padding items must carry the unused destinations
+// so that every bank still receives exactly N/64 items.
+#pragma once
+
+#include "common.hpp"
+
+namespace ts {
+
+template <int NW, int CAP>
+struct Router {
+    static constexpr int NCOL = CAP / 64;   // columns of the tile
+    static constexpr int CPW = NCOL / NW;   // columns per wave
+    static constexpr int M = CAP / 64;      // items per bank
+    static_assert(CPW * NW == NCOL, "capacity must split evenly over the waves");
+    static_assert(M >= 64, "tiles of at least 64 x 64 items");
+
+    // Route e[] (column w*CPW + j of the current order in e[j]) so that on return the
+    // LDS array A holds every item at its destination slot.  Contains barriers: every
+    // wave of the workgroup must call it.
+    static TS_DEV void route(uint64_t* A, int* wz, uint64_t (&e)[CPW], int w, int lane) {
+#pragma unroll 1
+        for (int L = 0; L < 6; ++L) {
+            const uint32_t lane8 = opaque((uint32_t)lane * 8u);
+            const uint32_t neg_lane8 = 0u - lane8;
+            const uint32_t own_base = lane8 + (uint32_t)(w * CPW * 512);  // column j at + 512 j
+            const int bit = 5 - L;                 // bank bit split at this level
+            const int seg_cols = NCOL >> L;        // columns per segment
+            const bool shared = seg_cols > CPW;    // segment spans several waves
+            int zb = 0;  // zeros of this segment in columns before this wave's first column
+            if (shared) {
+                int zc = 0;
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) zc += 64 - popc64(ballot((hi32(e[j]) >> bit) & 1u));
+                if (lane == 0) wz[w] = zc;
+                __syncthreads();  // all waves have read the previous level and posted counts
+                const int waves_per_seg = seg_cols / CPW;
+                const int first = (w / waves_per_seg) * waves_per_seg;
+                const int mine = (lane < NW) ? wz[lane] : 0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const int v = __builtin_amdgcn_readlane(mine, q);
+                    zb += (q >= first && q < w) ? v : 0;
+                }
+            }
+            int z = zb;
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int k = w * CPW + j;         // global column
+                const int kin = k % seg_cols;      // column inside its segment
+                if (!shared && kin == 0) z = 0;    // a new wave-local segment starts
+                const int seg_base = k - kin;      // first column of the segment
+                // ballot recomputed here rather than kept from the count loop (registers)
+                const uint64_t bal = ballot((hi32(e[j]) >> bit) & 1u);
+                const uint32_t r0 = count_below(~bal);
+                // zero: seg_base*64 + z + rank0; one: seg_end - 1 - (64 kin - z) - (lane - rank0)
+                const uint32_t z8 = (uint32_t)__builtin_amdgcn_readfirstlane((seg_base * 64 + z) * 8);
+                const uint32_t o8 = (uint32_t)__builtin_amdgcn_readfirstlane(
+                    ((seg_base + seg_cols) * 64 - 1 - 64 * kin + z) * 8);
+                const uint32_t a0 = r0 * 8u + z8;
+                const uint32_t a1 = (r0 * 8u + neg_lane8) + o8;
+                lds_store(A, select_by_mask(bal, a0, a1), e[j]);
+                z += 64 - popc64(bal);
+            }
+            if (shared) __syncthreads();  // the level is complete in every segment
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) e[j] = lds_load(A, own_base + 512u * j);
+        }
+        // ---- placement: group g = slots [g*M, (g+1)*M) holds the items for bank g.
+        //      Wave w performs steps t = w*CPW + j; lane l reads item (t + l) mod M of
+        //      group l and later writes it to its destination (bank l).
+        __syncthreads();  // every wave's groups are complete
+        const int lane_o = (int)opaque((uint32_t)lane);
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const int t = w * CPW + j;
+            const uint32_t slot = (uint32_t)lane_o * M + (uint32_t)((t + lane_o) & (M - 1));
+            e[j] = lds_load(A, slot * 8u);
+        }
+        __syncthreads();  // all groups read before any slot is overwritten
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const uint32_t dst = hi32(e[j]) & (uint32_t)(CAP - 1);
+            lds_store(A, dst * 8u, e[j]);
+        }
+        __syncthreads();  // A holds the tile in destination order
+    }
+};
+
+}  // namespace ts

@@ -1,0 +1,196 @@
+"""Torch-facing wrappers of the C interface (argument marshalling only).
+
+Tensors must live on the GPU; every 32-bit dtype (int32, uint32, float32) is
+accepted for keys / labels / payload words and moved bit-exactly.  Work is
+enqueued on the current torch stream.  Every step of the computation runs in
+libtilesort.so; nothing here computes on the host.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+
+_WORDS = (torch.int32, torch.float32, torch.uint32)
+_workspaces: dict = {}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace(device=None) -> torch.Tensor:
+    """Per-device workspace (error word + counters), zeroed once on creation."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else
+                       torch.device(device).index or 0)
+    ws = _workspaces.get(dev)
+    if ws is None:
+        lib = _lib.load()
+        nbytes = lib.ts_workspace_bytes(0, 0, 0, 0)
+        ws = torch.empty(nbytes // 4, dtype=torch.int32, device=dev)
+        _lib.check(lib.ts_workspace_init(_ptr(ws), nbytes, _stream(dev)))
+        _workspaces[dev] = ws
+    return ws
+
+
+def check_device_errors(device=None) -> None:
+    """Synchronise and raise if a kernel recorded a contract violation."""
+    ws = workspace(device)
+    _lib.check(_lib.load().ts_check(_ptr(ws), _stream(ws.device)))
+
+
+def _as_words(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype not in _WORDS:
+        raise TypeError(f"{name}: 32-bit dtype required, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _payload_layout(payload: Optional[torch.Tensor], n: int):
+    """payload: None, [N] (one channel) or [C, N] channel-planar.  Returns (channels, es, cs)."""
+    if payload is None:
+        return 0, 1, 0
+    if payload.dim() == 1:
+        assert payload.shape[0] == n, "payload length must match keys"
+        return 1, 1, 0
+    assert payload.dim() == 2 and payload.shape[1] == n, "payload must be [N] or [C, N]"
+    return payload.shape[0], 1, n
+
+
+def _offsets(offsets, n: int, device) -> torch.Tensor:
+    if offsets is None:
+        return torch.tensor([0, n], dtype=torch.int64, device=device)
+    if isinstance(offsets, torch.Tensor):
+        assert offsets.dtype == torch.int64
+        return offsets.to(device)
+    return torch.as_tensor(list(offsets), dtype=torch.int64, device=device)
+
+
+def _max_len(off: torch.Tensor, max_tile_len: Optional[int]) -> int:
+    if max_tile_len is not None:
+        return int(max_tile_len)
+    if off.numel() < 2:
+        return 0
+    return int((off[1:] - off[:-1]).max().item())
+
+
+def tile_partition(labels: torch.Tensor, payload: Optional[torch.Tensor] = None, offsets=None,
+                   num_classes: int = 64, max_tile_len: Optional[int] = None,
+                   schedule: str = "auto", want_perm: bool = False, validate: bool = False,
+                   labels_out: Optional[torch.Tensor] = None,
+                   payload_out: Optional[torch.Tensor] = None,
+                   perm_out: Optional[torch.Tensor] = None):
+    """Stable w-way partition of every tile (see tile_partition in include/tilesort.h).
+    Returns (labels_out, payload_out or None, perm or None)."""
+    labels = _as_words(labels, "labels")
+    n = labels.shape[0]
+    dev = labels.device
+    off = _offsets(offsets, n, dev)
+    ch, es, cs = _payload_layout(payload, n)
+    if payload is not None:
+        payload = _as_words(payload, "payload")
+        if payload_out is None:
+            payload_out = torch.empty_like(payload)
+    if labels_out is None:
+        labels_out = torch.empty_like(labels)
+    if want_perm and perm_out is None:
+        perm_out = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = workspace(dev)
+    flags = _lib.sched_flags(schedule) | (_lib.TS_FLAG_VALIDATE if validate else 0)
+    lib = _lib.load()
+    _lib.check(lib.tile_partition(_ptr(labels), _ptr(labels_out), _ptr(payload), _ptr(payload_out),
+                                  ch, es, cs, num_classes, _ptr(perm_out), _ptr(off),
+                                  off.numel() - 1, _max_len(off, max_tile_len), flags, _ptr(ws),
+                                  ws.numel() * 4, _stream(dev)))
+    return labels_out, payload_out, perm_out
+
+
+def tile_permute(x: torch.Tensor, pi: torch.Tensor, direction: str = "scatter", offsets=None,
+                 max_tile_len: Optional[int] = None, schedule: str = "auto",
+                 validate: bool = False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Apply tile-local permutations: scatter out[pi[i]] = x[i], gather out[i] = x[pi[i]].
+    ``x`` is [N] or [C, N] (channel-planar)."""
+    x = _as_words(x, "x")
+    n = x.shape[-1]
+    dev = x.device
+    assert pi.dtype == torch.int32 and pi.shape[0] == n and pi.is_cuda
+    off = _offsets(offsets, n, dev)
+    ch, es, cs = _payload_layout(x, n)
+    if out is None:
+        out = torch.empty_like(x)
+    d = {"scatter": _lib.TS_SCATTER, "gather": _lib.TS_GATHER}[direction]
+    ws = workspace(dev)
+    flags = _lib.sched_flags(schedule) | (_lib.TS_FLAG_VALIDATE if validate else 0)
+    lib = _lib.load()
+    _lib.check(lib.tile_permute(_ptr(x), _ptr(out), ch, es, cs, _ptr(pi), d, _ptr(off),
+                                off.numel() - 1, _max_len(off, max_tile_len), flags, _ptr(ws),
+                                ws.numel() * 4, _stream(dev)))
+    return out
+
+
+def tile_sort(keys: torch.Tensor, payload: Optional[torch.Tensor] = None, offsets=None,
+              max_tile_len: Optional[int] = None, f32_ordered: bool = False,
+              schedule: str = "auto", want_perm: bool = True,
+              keys_out: Optional[torch.Tensor] = None,
+              payload_out: Optional[torch.Tensor] = None,
+              perm_out: Optional[torch.Tensor] = None):
+    """Stable ascending sort of every tile.  Returns (keys_out, payload_out or None, perm)."""
+    keys = _as_words(keys, "keys")
+    n = keys.shape[0]
+    dev = keys.device
+    off = _offsets(offsets, n, dev)
+    ch, es, cs = _payload_layout(payload, n)
+    if payload is not None:
+        payload = _as_words(payload, "payload")
+        if payload_out is None:
+            payload_out = torch.empty_like(payload)
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if want_perm and perm_out is None:
+        perm_out = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = workspace(dev)
+    flags = _lib.sched_flags(schedule) | (_lib.TS_FLAG_F32_ORDERED if f32_ordered else 0)
+    lib = _lib.load()
+    _lib.check(lib.tile_sort(_ptr(keys), _ptr(keys_out), _ptr(payload), _ptr(payload_out), ch, es,
+                             cs, _ptr(perm_out), _ptr(off), off.numel() - 1,
+                             _max_len(off, max_tile_len), flags, _ptr(ws), ws.numel() * 4,
+                             _stream(dev)))
+    return keys_out, payload_out, perm_out
+
+
+def copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """HBM reference copy (16-byte vector loads and stores)."""
+    assert src.is_cuda and dst.is_cuda and src.numel() * src.element_size() <= dst.numel() * dst.element_size()
+    lib = _lib.load()
+    _lib.check(lib.ts_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(), _stream(src.device)))
+
+
+def lds_probe(lane_words: Sequence[int], op: str = "read", width: int = 1, iters: int = 256,
+              waves: int = 1, groups: int = 1, device=None):
+    """Run the LDS access probe; returns (cycles per wave [tensor], sink)."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    lw = torch.as_tensor(list(lane_words), dtype=torch.int32, device=dev)
+    assert lw.numel() == 64
+    nw = waves * groups
+    cycles = torch.zeros(nw, dtype=torch.int64, device=dev)
+    sink = torch.zeros(nw * 64, dtype=torch.int32, device=dev)
+    opi = {"read": 0, "write": 1, "bpermute": 2}[op]
+    lib = _lib.load()
+    _lib.check(lib.ts_lds_probe(_ptr(lw), opi, width, iters, waves, groups, _ptr(cycles),
+                                _ptr(sink), _stream(dev)))
+    return cycles, sink
+
+
+def tune(knob: str, value: int) -> None:
+    """Override one entry of the library's kernel-selection table (see ts_tune)."""
+    _lib.check(_lib.load().ts_tune(knob.encode(), int(value)))

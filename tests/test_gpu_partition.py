@@ -1,0 +1,99 @@
+"""GPU parity of tile_partition against the CPU oracle (bit-exact), through the C interface."""
+import numpy as np
+import pytest
+
+from paper_1507_01391_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = ["split", "naive"]
+
+
+@pytest.fixture(scope="module")
+def ts():
+    import paper_1507_01391_amd as ts
+    return ts
+
+
+def run_and_compare(ts, oracle, labels, payload, off, num_classes, schedule, max_len=None):
+    from tests.gpu_util import dev, host_i32, host_u32
+    want_l, want_p, want_perm = oracle.tile_partition(labels, None if payload is None else payload.view(np.uint32),
+                                                      off, num_classes=num_classes, nthreads=8)
+    lab_out, pay_out, perm = ts.tile_partition(dev(labels), None if payload is None else dev(payload),
+                                               dev(off), num_classes=num_classes,
+                                               max_tile_len=max_len, schedule=schedule,
+                                               want_perm=True)
+    ts.check_device_errors()
+    assert np.array_equal(host_u32(lab_out), want_l)
+    assert np.array_equal(host_i32(perm), want_perm)
+    if payload is not None:
+        assert np.array_equal(host_u32(pay_out), want_p)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_exact_copies_4096(ts, oracle, schedule):
+    labels, payload, off = inputs.partition(seed=21, num_tiles=300, n=4096)
+    run_and_compare(ts, oracle, labels, payload, off, 64, schedule)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("num_classes", [1, 2, 5, 17, 64])
+def test_uneven_tiles_random_labels(ts, oracle, schedule, num_classes):
+    rng = np.random.default_rng(num_classes)
+    sizes = np.concatenate([[0, 1, 2, 63, 64, 65, 127, 4095, 4096, 4033],
+                            rng.integers(0, 4097, size=60)])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    labels = rng.integers(0, num_classes, size=off[-1], dtype=np.uint32)
+    payload = rng.standard_normal(off[-1]).astype(np.float32)
+    run_and_compare(ts, oracle, labels, payload, off, num_classes, schedule, max_len=4096)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("cap", [1024, 2048, 8192, 16384])
+def test_large_tiles(ts, oracle, schedule, cap):
+    rng = np.random.default_rng(cap)
+    sizes = np.array([cap, cap - 1, cap // 2 + 7, 1, 0, cap])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    labels = rng.integers(0, 64, size=off[-1], dtype=np.uint32)
+    payload = rng.integers(0, 2**32, size=off[-1], dtype=np.uint32)
+    run_and_compare(ts, oracle, labels, payload, off, 64, schedule, max_len=cap)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8, 16, 104, 108])
+def test_wave_count_variants(ts, oracle, waves):
+    labels, payload, off = inputs.partition(seed=30 + waves, num_tiles=40, n=4096)
+    ts.tune("partition_waves_4096", waves)
+    try:
+        run_and_compare(ts, oracle, labels, payload, off, 64, "split", max_len=4096)
+    finally:
+        ts.tune("partition_waves_4096", 8)
+
+
+def test_no_payload_and_degenerate_labels(ts, oracle):
+    n = 4096 * 5
+    off = np.arange(6, dtype=np.int64) * 4096
+    for labels in (np.zeros(n, np.uint32), np.full(n, 63, np.uint32),
+                   np.tile(np.arange(64, dtype=np.uint32), n // 64),
+                   np.repeat(np.arange(64, dtype=np.uint32)[::-1], n // 64)):
+        run_and_compare(ts, oracle, labels, None, off, 64, "split")
+
+
+def test_validate_flags_bad_label(ts):
+    import torch
+    from tests.gpu_util import dev
+    labels = np.zeros(4096, np.uint32)
+    labels[77] = 64
+    ts.tile_partition(dev(labels), None, dev(np.array([0, 4096], np.int64)), num_classes=64,
+                      validate=True)
+    with pytest.raises(RuntimeError, match="num_classes"):
+        ts.check_device_errors()
+    torch.cuda.synchronize()
+
+
+def test_tile_longer_than_capacity_is_reported(ts):
+    from tests.gpu_util import dev
+    labels = np.zeros(8192, np.uint32)
+    # max_tile_len understates the real length: the kernel skips the tile and flags it
+    ts.tile_partition(dev(labels), None, dev(np.array([0, 8192], np.int64)), max_tile_len=4096)
+    with pytest.raises(RuntimeError, match="capacity"):
+        ts.check_device_errors()

@@ -1,0 +1,74 @@
+"""GPU parity of tile_permute (scatter and gather) against the CPU oracle, bit-exact."""
+import numpy as np
+import pytest
+
+from paper_1507_01391_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ts():
+    import paper_1507_01391_amd as ts
+    return ts
+
+
+def run_and_compare(ts, oracle, x, pi, off, direction, schedule="split", max_len=None):
+    from tests.gpu_util import dev, host_u32
+    d = oracle.SCATTER if direction == "scatter" else oracle.GATHER
+    want = oracle.tile_permute(x.view(np.uint32), pi, d, off, nthreads=8)
+    got = ts.tile_permute(dev(x), dev(pi), direction, dev(off), max_tile_len=max_len,
+                          schedule=schedule)
+    ts.check_device_errors()
+    assert np.array_equal(host_u32(got).reshape(want.shape), want)
+
+
+@pytest.mark.parametrize("direction", ["scatter", "gather"])
+@pytest.mark.parametrize("family", ["uniform", "transpose", "bitrev", "identity"])
+@pytest.mark.parametrize("schedule", ["split", "naive"])
+def test_families_8192(ts, oracle, direction, family, schedule):
+    x, pi, _, off = inputs.permutation(seed=40, num_tiles=64, n=8192, family=family)
+    run_and_compare(ts, oracle, x, pi, off, direction, schedule)
+
+
+@pytest.mark.parametrize("direction", ["scatter", "gather"])
+@pytest.mark.parametrize("cap", [4096, 8192, 16384])
+def test_uneven_tiles(ts, oracle, direction, cap):
+    rng = np.random.default_rng(cap + (direction == "gather"))
+    sizes = np.concatenate([[0, 1, 2, 63, 64, 65, cap, cap - 1], rng.integers(0, cap + 1, size=20)])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = rng.integers(0, 2**32, size=off[-1], dtype=np.uint32)
+    pi = np.concatenate([rng.permutation(int(s)) for s in sizes]).astype(np.int32)
+    run_and_compare(ts, oracle, x, pi, off, direction, max_len=cap)
+
+
+@pytest.mark.parametrize("direction", ["scatter", "gather"])
+def test_multichannel_planar(ts, oracle, direction):
+    rng = np.random.default_rng(9)
+    x, pi, _, off = inputs.permutation(seed=41, num_tiles=20, n=4096, family="uniform")
+    x3 = np.stack([x, -x, x * 2]).astype(np.float32)
+    run_and_compare(ts, oracle, x3, pi, off, direction)
+
+
+def test_roundtrip_scatter_then_gather(ts):
+    from tests.gpu_util import dev, host_u32
+    x, pi, _, off = inputs.permutation(seed=42, num_tiles=32, n=8192, family="uniform")
+    y = ts.tile_permute(dev(x), dev(pi), "scatter", dev(off))
+    z = ts.tile_permute(y, dev(pi), "gather", dev(off))
+    assert np.array_equal(host_u32(z), x.view(np.uint32))
+
+
+@pytest.mark.parametrize("direction", ["scatter", "gather"])
+def test_validate_reports_non_permutation(ts, direction):
+    from tests.gpu_util import dev
+    pi = np.arange(4096, dtype=np.int32)
+    pi[10] = pi[11]                      # duplicate, 10's slot is never written
+    x = np.arange(4096, dtype=np.uint32)
+    ts.tile_permute(dev(x), dev(pi), direction, dev(np.array([0, 4096], np.int64)), validate=True)
+    with pytest.raises(RuntimeError, match="permutation"):
+        ts.check_device_errors()
+    pi = np.arange(4096, dtype=np.int32)
+    pi[5] = 5000                         # out of range
+    ts.tile_permute(dev(x), dev(pi), direction, dev(np.array([0, 4096], np.int64)), validate=True)
+    with pytest.raises(RuntimeError, match="permutation"):
+        ts.check_device_errors()
