@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark: batched 64-way partition of 65536 tiles x 4096 uint32 labels on one MI355X.
+
+One step = one tile_partition call over the whole batch (load every tile from
+HBM, partition it in LDS without bank conflicts, store labels and payload).
+Prints ONE JSON line (see the keys below).  Only one GPU is used; --gpus > 1
+exits with a message.
+
+  python bench.py [--steps K] [--warmup W] [--config c2|c3|c1] [--no-cpu] [--no-extra]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X published HBM3E bandwidth
+METRIC = "sorted uint32 keys/s per GPU + LDS bank conflicts/access; fwd+bwd permute GB/s"
+# Algorithmic bytes per key of the partition kernel: label in + payload in + label out
+# + payload out, 4 bytes each.
+PARTITION_BYTES_PER_KEY = 16
+# Permutation, per direction: value in + pi in + value out.
+PERMUTE_BYTES_PER_ELEM = 12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_launches(fn, steps, warmup, torch):
+    """Run fn() warmup times, then steps times with a CUDA event pair around every call
+    on the current stream.  Returns (total_ms over the timed region, mean ms per launch)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    per = [a.elapsed_time(b) for a, b in ev]
+    return wall_ms, float(np.mean(per)), per
+
+
+def cpu_baseline_partition(labels, payload, offsets, oracle, min_seconds=10.0):
+    """Time the oracle on a bounded sample of tiles; returns (keys/s, cores, sample text)."""
+    cores = min(os.cpu_count() or 1, 16)
+    tiles = min(16384, len(offsets) - 1)
+    n = int(offsets[tiles])
+    lab = np.ascontiguousarray(labels[:n])
+    pay = np.ascontiguousarray(payload[:n].view(np.uint32))
+    off = np.ascontiguousarray(offsets[:tiles + 1])
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.tile_partition(lab, pay, off, num_classes=64, nthreads=cores)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds or reps >= 50:
+            break
+    return n * reps / el, cores, f"{tiles} of {len(offsets) - 1} tiles ({n} keys), {reps} repetitions, {el:.1f} s"
+
+
+def bench_c2(args, torch, ts, inputs):
+    T = args.tiles
+    log(f"[bench] generating C2 inputs: {T} tiles x 4096 ...")
+    labels, payload, offsets = inputs.partition(num_tiles=T)
+    n_total = labels.shape[0]
+    d_lab = torch.from_numpy(labels.view(np.int32)).cuda()
+    d_pay = torch.from_numpy(payload).cuda()
+    d_off = torch.from_numpy(offsets).cuda()
+    lab_out = torch.empty_like(d_lab)
+    pay_out = torch.empty_like(d_pay)
+    torch.cuda.synchronize()
+
+    def step():
+        ts.tile_partition(d_lab, d_pay, d_off, num_classes=64, max_tile_len=4096,
+                          labels_out=lab_out, payload_out=pay_out)
+
+    log("[bench] timing the conflict-free partition ...")
+    wall_ms, mean_ms, _ = timed_launches(step, args.steps, args.warmup, torch)
+    ts.check_device_errors()
+    ms_per_step = wall_ms / args.steps
+    value = n_total / (ms_per_step / 1e3)
+    achieved = PARTITION_BYTES_PER_KEY * n_total / (mean_ms / 1e3) / 1e9
+
+    # parity on sampled tiles (oracle computes them one by one)
+    from oracle import oracle as orc
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(T, size=min(16, T), replace=False))
+    lo = lab_out.cpu().numpy().view(np.uint32)
+    po = pay_out.cpu().numpy().view(np.uint32)
+    ok = True
+    for t in sample:
+        a, b = int(offsets[t]), int(offsets[t + 1])
+        wl, wp, _ = orc.tile_partition(labels[a:b], payload[a:b].view(np.uint32), num_classes=64)
+        ok &= bool(np.array_equal(lo[a:b], wl) and np.array_equal(po[a:b], wp))
+    if not ok:
+        log("[bench] PARITY FAILURE on sampled tiles")
+
+    extra = {"parity_sampled_tiles": f"{len(sample)} tiles bit-exact" if ok else "MISMATCH"}
+    if not args.no_extra:
+        def naive():
+            ts.tile_partition(d_lab, d_pay, d_off, num_classes=64, max_tile_len=4096,
+                              schedule="naive", labels_out=lab_out, payload_out=pay_out)
+        log("[bench] timing the naive-LDS batched form ...")
+        w2, m2, _ = timed_launches(naive, max(3, args.steps // 2), 2, torch)
+        extra["naive_lds_batched_keys_per_s"] = n_total / (w2 / max(3, args.steps // 2) / 1e3)
+        # one tile per launch on a sample of tiles
+        sample_tiles = 1024
+        one_off = torch.tensor([0, 4096], dtype=torch.int64, device="cuda")
+
+        def per_launch():
+            for t in range(sample_tiles):
+                ts.tile_partition(d_lab[t * 4096:(t + 1) * 4096], d_pay[t * 4096:(t + 1) * 4096],
+                                  one_off, num_classes=64, max_tile_len=4096, schedule="naive",
+                                  labels_out=lab_out[t * 4096:(t + 1) * 4096],
+                                  payload_out=pay_out[t * 4096:(t + 1) * 4096])
+        log("[bench] timing the naive one-tile-per-launch form ...")
+        w3, _, _ = timed_launches(per_launch, 2, 1, torch)
+        extra["naive_one_tile_per_launch_keys_per_s"] = sample_tiles * 4096 / (w3 / 2 / 1e3)
+        extra["naive_one_tile_per_launch_sample"] = f"{sample_tiles} tiles, one launch each"
+        # copy kernel: achievable HBM bandwidth on this machine
+        buf = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        buf2 = torch.empty_like(buf)
+        w4, m4, _ = timed_launches(lambda: ts.copy(buf, buf2), 10, 3, torch)
+        extra["hbm_copy_GBps"] = 2 * (1 << 30) / (m4 / 1e3) / 1e9
+        del buf, buf2
+        # C3 fwd + bwd permutation rate (secondary metric)
+        extra.update(bench_c3(args, torch, ts, inputs, quick=True))
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        v, cores, sample_txt = cpu_baseline_partition(labels, payload, offsets, orc)
+        cpu = {"value": v, "unit": "keys/s", "cores": cores, "kind": "oracle", "sample": sample_txt}
+
+    return {
+        "metric": METRIC,
+        "value": value,
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded numpy PCG64; no dataset in the paper)",
+        "config": {"workload": f"batched 64-way partition: {T} tiles x 4096 uint32 labels "
+                               "(exactly 64 copies of each label per tile, shuffled), "
+                               "1-channel fp32 payload N(0,1)",
+                   "tiles": T, "tile_len": 4096, "num_classes": 64, "payload_channels": 1,
+                   "kernel": "partition_split (alternating-direction binary splits)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "bytes_per_key": PARTITION_BYTES_PER_KEY,
+                     "kernel_mean_ms": mean_ms},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+
+
+def bench_c3(args, torch, ts, inputs, quick=False):
+    T = 4096 if quick else args.tiles3
+    x, pi, g, off = inputs.permutation(num_tiles=T, n=8192)
+    dx = torch.from_numpy(x).cuda()
+    dpi = torch.from_numpy(pi).cuda()
+    dg = torch.from_numpy(g).cuda()
+    doff = torch.from_numpy(off).cuda()
+    y = torch.empty_like(dx)
+    gx = torch.empty_like(dx)
+
+    def fwd_bwd():
+        ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y)
+        ts.tile_permute(dg, dpi, "gather", doff, max_tile_len=8192, out=gx)
+
+    w, m, _ = timed_launches(fwd_bwd, 10, 3, torch)
+    n = T * 8192
+    return {"c3_permute_fwd_bwd_GBps": 2 * PERMUTE_BYTES_PER_ELEM * n / (w / 10 / 1e3) / 1e9,
+            "c3_permute_tiles": T}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tiles", type=int, default=65536)
+    ap.add_argument("--tiles3", type=int, default=16384)
+    ap.add_argument("--config", default="c2", choices=["c2"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 1 GiB copy kernel (reference for HBM traffic counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the workload is per-tile independent and has no "
+              f"cross-GPU exchange); got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1507_01391_amd as ts
+    from paper_1507_01391_amd import inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    if args.calib_copy:
+        buf = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        buf2 = torch.empty_like(buf)
+        ts.copy(buf, buf2)
+        torch.cuda.synchronize()
+        del buf, buf2
+    res = bench_c2(args, torch, ts, inputs)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
