@@ -112,10 +112,9 @@ const char* ts_last_error(void) { return g_last_error.c_str(); }
 const char* ts_version(void) { return "tilesort 0.1 (gfx950)"; }
 
 size_t ts_workspace_bytes(int op, int64_t num_tiles, int64_t max_tile_len, uint32_t channels) {
-    (void)op;
-    (void)num_tiles;
-    (void)max_tile_len;
-    (void)channels;
+    // tile_sort with a payload and no perm_out keeps the permutation in the workspace
+    if (op == TS_OP_SORT && channels > 0 && num_tiles > 0 && max_tile_len > 0)
+        return kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
     return kWorkspaceBytes;
 }
 
@@ -226,10 +225,59 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
                     int64_t chan_stride, int32_t* perm_out, const int64_t* tile_offsets,
                     int64_t num_tiles, int64_t max_tile_len, uint32_t flags, void* workspace,
                     size_t workspace_bytes, void* stream) {
-    (void)keys_in; (void)keys_out; (void)payload_in; (void)payload_out; (void)channels;
-    (void)elem_stride; (void)chan_stride; (void)perm_out; (void)tile_offsets; (void)num_tiles;
-    (void)max_tile_len; (void)flags; (void)workspace; (void)workspace_bytes; (void)stream;
-    return fail(TS_ERR_UNSUPPORTED, "tile_sort: not built yet");
+    ts_status st = check_common(tile_offsets, num_tiles, max_tile_len, workspace, workspace_bytes);
+    if (st != TS_OK) return st;
+    if (num_tiles > 0 && keys_in == nullptr) return fail(TS_ERR_INVALID, "tile_sort: keys_in is NULL");
+    if (keys_in != nullptr && keys_in == keys_out)
+        return fail(TS_ERR_INVALID, "tile_sort: keys_in and keys_out alias");
+    st = check_payload(payload_in, payload_out, channels, elem_stride, chan_stride, true);
+    if (st != TS_OK) return st;
+    int sched = sched_of(flags);
+    if (sched == TS_SCHED_AUTO) sched = (max_tile_len <= 4096) ? TS_SCHED_BITONIC : TS_SCHED_SPLIT;
+    if (sched != TS_SCHED_SPLIT && sched != TS_SCHED_THM2 && sched != TS_SCHED_BITONIC &&
+        sched != TS_SCHED_NAIVE)
+        return fail(TS_ERR_UNSUPPORTED, "tile_sort: schedule %d not available", sched);
+    const int64_t cap = (sched == TS_SCHED_NAIVE) ? 16384 : ts::sort_capacity(sched);
+    if (max_tile_len > cap)
+        return fail(TS_ERR_UNSUPPORTED, "tile_sort: max_tile_len %lld > %lld for this schedule",
+                    (long long)max_tile_len, (long long)cap);
+    // The payload is moved by a gather through the permutation; without perm_out the
+    // permutation lives in the workspace after the 256-byte header.
+    int32_t* perm = perm_out;
+    if (channels > 0 && perm == nullptr) {
+        const size_t need = kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
+        if (workspace_bytes < need)
+            return fail(TS_ERR_WORKSPACE, "tile_sort: payload without perm_out needs %zu workspace bytes", need);
+        perm = (int32_t*)((char*)workspace + kWorkspaceBytes);
+    }
+    ts::SortArgs a{};
+    a.keys_in = keys_in;
+    a.keys_out = keys_out;
+    a.pay = ts::PayloadRef{payload_in, payload_out, channels, elem_stride, chan_stride};
+    a.perm_out = perm;
+    a.offsets = tile_offsets;
+    a.num_tiles = num_tiles;
+    a.f32 = (flags & TS_FLAG_F32_ORDERED) ? 1u : 0u;
+    a.err = (uint32_t*)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = (sched == TS_SCHED_NAIVE) ? ts::launch_sort_naive(a, max_tile_len, s)
+                                             : ts::launch_sort(a, max_tile_len, sched, s);
+    if (e != hipSuccess) return hip_status(e, "tile_sort launch");
+    if (channels > 0 && num_tiles > 0) {
+        // the payload is not part of the composite: gather it by the permutation
+        // (a conflict-free routing per tile), or by a direct LDS gather for the baseline
+        ts::PermuteArgs p{};
+        p.pay = a.pay;
+        p.pi = perm;
+        p.direction = TS_GATHER;
+        p.offsets = tile_offsets;
+        p.num_tiles = num_tiles;
+        p.err = a.err;
+        e = (sched == TS_SCHED_NAIVE) ? ts::launch_permute_naive(p, max_tile_len, s)
+                                      : ts::launch_permute_split(p, max_tile_len < 4096 ? 4096 : max_tile_len, s);
+        if (e != hipSuccess) return hip_status(e, "tile_sort payload gather launch");
+    }
+    return TS_OK;
 }
 
 ts_status ts_tune(const char* knob, int value) {

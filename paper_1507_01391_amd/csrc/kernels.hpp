@@ -66,6 +66,8 @@ hipError_t launch_partition_thm2(const PartitionArgs& a, int64_t max_len, hipStr
 hipError_t launch_permute_split(const PermuteArgs& a, int64_t max_len, hipStream_t s);
 hipError_t launch_permute_naive(const PermuteArgs& a, int64_t max_len, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, int64_t max_len, int sched, hipStream_t s);
+hipError_t launch_sort_split(const SortArgs& a, int64_t max_len, hipStream_t s);
+hipError_t launch_sort_naive(const SortArgs& a, int64_t max_len, hipStream_t s);
 
 int64_t partition_split_capacity();
 void set_partition_waves(int nw);

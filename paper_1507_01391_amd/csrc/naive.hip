@@ -190,7 +190,110 @@ hipError_t launch_pmn(const PermuteArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// LSD radix sort with 4-bit digits: per pass, per-column multisplit ranks and one
+// direct LDS scatter (bank conflicts).  Items are (ordered key, position); the tile
+// is padded to the capacity with keys 0xFFFFFFFF and positions >= n.
+template <int NW, int CAP>
+__global__ __launch_bounds__(NW * 64) void sort_naive_kernel(SortArgs a) {
+    constexpr int CPW = CAP / 64 / NW;
+    __shared__ uint64_t A[CAP];
+    __shared__ int cnt[NW][16];
+    __shared__ int start[NW][16];
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int64_t t = blockIdx.x; t < a.num_tiles; t += gridDim.x) {
+        const int64_t o = a.offsets[t];
+        const int64_t len = a.offsets[t + 1] - o;
+        if (len > CAP) {
+            if (threadIdx.x == 0) atomicOr(a.err, ERR_TILE_TOO_LONG);
+            continue;
+        }
+        const int n = (int)len;
+        uint32_t kv[CPW];
+        if (n > 0) load_columns<CPW>(a.keys_in, 1, o, n, w * CPW, lane, kv);
+        uint64_t e[CPW];
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const int i = 64 * (w * CPW + j) + lane;
+            const uint32_t key = (i < n) ? (a.f32 ? f32_to_ordered(kv[j]) : kv[j]) : 0xFFFFFFFFu;
+            e[j] = pack(key, (uint32_t)i);
+        }
+#pragma unroll 1
+        for (int pass = 0; pass < 8; ++pass) {
+            const int sh = 4 * pass;
+            if (lane < 16) cnt[w][lane] = 0;
+            int rank[CPW];
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const uint32_t d = (hi32(e[j]) >> sh) & 15u;
+                uint64_t match = ~0ull;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint64_t bb = ballot((d >> b) & 1u);
+                    match &= ((d >> b) & 1u) ? bb : ~bb;
+                }
+                const int inr = (int)count_below(match);
+                const int tot = popc64(match);
+                const int base = cnt[w][d];
+                rank[j] = base + inr;
+                if (inr == tot - 1) cnt[w][d] = base + tot;
+            }
+            __syncthreads();
+            if (w == 0 && lane < 16) {
+                int tot = 0;
+                for (int q = 0; q < NW; ++q) tot += cnt[q][lane];
+                int excl = 0;
+                for (int d2 = 0; d2 < 16; ++d2) {
+                    const int td = __shfl(tot, d2, 64);
+                    excl += (d2 < lane) ? td : 0;
+                }
+                int run = excl;
+                for (int q = 0; q < NW; ++q) {
+                    start[q][lane] = run;
+                    run += cnt[q][lane];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const uint32_t d = (hi32(e[j]) >> sh) & 15u;
+                A[start[w][d] + rank[j]] = e[j];  // direct scatter: bank conflicts
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) e[j] = A[64 * (w * CPW + j) + lane];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const int v = 64 * (w * CPW + j) + lane;
+            if (v < n) {
+                const uint32_t key = hi32(e[j]);
+                if (a.keys_out) store_item(a.keys_out, 1, o, v, a.f32 ? ordered_to_f32(key) : key);
+                if (a.perm_out) store_item(a.perm_out, 1, o, v, (int32_t)lo32(e[j]));
+            }
+        }
+    }
+}
+
+template <int NW, int CAP>
+hipError_t launch_sn(const SortArgs& a, hipStream_t s) {
+    auto kern = sort_naive_kernel<NW, CAP>;
+    const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_sort_naive(const SortArgs& a, int64_t max_len, hipStream_t s) {
+    if (a.num_tiles == 0) return hipSuccess;
+    if (max_len <= 1024) return launch_sn<4, 1024>(a, s);
+    if (max_len <= 2048) return launch_sn<4, 2048>(a, s);
+    if (max_len <= 4096) return launch_sn<8, 4096>(a, s);
+    if (max_len <= 8192) return launch_sn<8, 8192>(a, s);
+    return launch_sn<16, 16384>(a, s);
+}
 
 hipError_t launch_permute_naive(const PermuteArgs& a, int64_t max_len, hipStream_t s) {
     if (a.num_tiles == 0) return hipSuccess;

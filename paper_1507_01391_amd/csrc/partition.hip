@@ -32,6 +32,25 @@ namespace ts {
 
 namespace {
 
+// Arguments of the split kernel, for both uses: the stable partition (MODE 0: item =
+// label + position + one payload word) and the LSD radix sort of 32-bit keys (MODE 1:
+// item = ordered key + position).
+struct SplitArgs {
+    const uint32_t* keys_in;    // labels or keys
+    uint32_t* keys_out;
+    const uint32_t* pay_in;     // MODE 0 only, one channel
+    uint32_t* pay_out;
+    int64_t pay_es;
+    uint32_t has_pay;
+    int32_t* perm_out;
+    int64_t num_tiles;
+    uint32_t num_classes;       // MODE 0: labels must be below this
+    int nbits;                  // bits to split on
+    uint32_t validate;
+    uint32_t f32;               // MODE 1: keys are binary32 patterns
+    uint32_t* err;
+};
+
 template <int CPW>
 struct TileLoad {
     int64_t o;   // first item of the tile
@@ -43,7 +62,7 @@ struct TileLoad {
 // Issue the global loads of one tile (no waits).  Lanes past the end read item 0 of
 // the tile (always valid when n > 0) and are replaced by padding later.
 template <int CPW, int CAP>
-TS_DEV void issue_tile_load(const PartitionArgs& a, const int64_t* __restrict__ offs, int64_t t,
+TS_DEV void issue_tile_load(const SplitArgs& a, const int64_t* __restrict__ offs, int64_t t,
                             int w, int lane, TileLoad<CPW>& L) {
     if (t >= a.num_tiles) {
         L.n = -1;
@@ -53,15 +72,14 @@ TS_DEV void issue_tile_load(const PartitionArgs& a, const int64_t* __restrict__ 
     const int64_t len = offs[t + 1] - o;
     L.o = o;
     L.n = (len > CAP) ? -2 : (int)len;
-    const bool has_pay = a.pay.channels > 0;
     if (L.n <= 0) return;
-    load_columns<CPW>(a.labels_in, 1, o, L.n, w * CPW, lane, L.lab);
-    if (has_pay) load_columns<CPW>(a.pay.in, a.pay.es, o, L.n, w * CPW, lane, L.pay);
+    load_columns<CPW>(a.keys_in, 1, o, L.n, w * CPW, lane, L.lab);
+    if (a.has_pay) load_columns<CPW>(a.pay_in, a.pay_es, o, L.n, w * CPW, lane, L.pay);
 }
 
-template <int NW, int CAP, int WPE>
+template <int NW, int CAP, int WPE, int MODE>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
-void partition_split_kernel(PartitionArgs a, const int64_t* __restrict__ offs) {
+void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
     constexpr int CPW = CAP / 64 / NW;  // columns per wave
     // Narrow waves have room to load the next tile during this one; wide ones load
     // each tile when they start it.
@@ -70,8 +88,8 @@ void partition_split_kernel(PartitionArgs a, const int64_t* __restrict__ offs) {
     __shared__ int wz[NW];
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const uint32_t lmask = (1u << a.nbits) - 1u;
-    const bool has_pay = a.pay.channels > 0;
+    const uint32_t lmask = (MODE == 0) ? (1u << a.nbits) - 1u : 0xFFFFFFFFu;
+    const bool has_pay = a.has_pay != 0;
 
     TileLoad<CPW> L;
     int64_t t = blockIdx.x;
@@ -91,7 +109,7 @@ void partition_split_kernel(PartitionArgs a, const int64_t* __restrict__ offs) {
         constexpr int N = CAP;
 
         // ---- items of this tile: column k, lane l holds item 64k + l.  Padding items
-        //      carry the largest label and a position >= n, so they end up last.
+        //      carry the largest label (key) and a position >= n, so they end up last.
         uint64_t e[CPW];
         bool bad = false;
 #pragma unroll
@@ -100,11 +118,15 @@ void partition_split_kernel(PartitionArgs a, const int64_t* __restrict__ offs) {
             uint32_t lab = lmask, pay = 0;
             if (i < n) {
                 lab = L.lab[j];
-                bad |= lab >= a.num_classes;
-                lab &= lmask;
-                pay = L.pay[j];
+                if (MODE == 0) {
+                    bad |= lab >= a.num_classes;
+                    lab &= lmask;
+                    pay = L.pay[j];
+                } else if (a.f32) {
+                    lab = f32_to_ordered(lab);
+                }
             }
-            e[j] = pack(((uint32_t)i << 16) | lab, pay);
+            e[j] = (MODE == 0) ? pack(((uint32_t)i << 16) | lab, pay) : pack(lab, (uint32_t)i);
         }
         if (a.validate) flag_error(a.err, bad, ERR_BAD_LABEL);
 
@@ -179,20 +201,25 @@ void partition_split_kernel(PartitionArgs a, const int64_t* __restrict__ offs) {
             const int v = 64 * (w * CPW + j) + lane;
             if (v < n) {
                 const uint32_t h = hi32(e[j]);
-                if (a.labels_out) store_item(a.labels_out, 1, o, v, h & 0xFFFFu);
-                if (has_pay) store_item(a.pay.out, a.pay.es, o, v, lo32(e[j]));
-                if (a.perm_out) store_item(a.perm_out, 1, o, v, (int32_t)(h >> 16));
+                if (MODE == 0) {
+                    if (a.keys_out) store_item(a.keys_out, 1, o, v, h & 0xFFFFu);
+                    if (has_pay) store_item(a.pay_out, a.pay_es, o, v, lo32(e[j]));
+                    if (a.perm_out) store_item(a.perm_out, 1, o, v, (int32_t)(h >> 16));
+                } else {
+                    if (a.keys_out) store_item(a.keys_out, 1, o, v, a.f32 ? ordered_to_f32(h) : h);
+                    if (a.perm_out) store_item(a.perm_out, 1, o, v, (int32_t)lo32(e[j]));
+                }
             }
         }
         if (!PREFETCH) issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
     }
 }
 
-template <int NW, int CAP, int WPE = 0>
-hipError_t launch_split(const PartitionArgs& a, hipStream_t s) {
-    auto kern = partition_split_kernel<NW, CAP, WPE>;
+template <int NW, int CAP, int WPE = 0, int MODE = 0>
+hipError_t launch_split(const SplitArgs& a, const int64_t* offs, hipStream_t s) {
+    auto kern = split_kernel<NW, CAP, WPE, MODE>;
     const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, a.offsets);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, offs);
     return hipGetLastError();
 }
 
@@ -204,23 +231,55 @@ int64_t partition_split_capacity() { return 16384; }
 static int g_part_nw4096 = 8;
 void set_partition_waves(int nw) { g_part_nw4096 = nw; }
 
-hipError_t launch_partition_split(const PartitionArgs& a, int64_t max_len, hipStream_t s) {
-    if (a.num_tiles == 0) return hipSuccess;
-    if (max_len <= 1024) return launch_split<4, 1024>(a, s);
-    if (max_len <= 2048) return launch_split<4, 2048>(a, s);
+hipError_t launch_partition_split(const PartitionArgs& p, int64_t max_len, hipStream_t s) {
+    if (p.num_tiles == 0) return hipSuccess;
+    SplitArgs a{};
+    a.keys_in = p.labels_in;
+    a.keys_out = p.labels_out;
+    a.pay_in = p.pay.in;
+    a.pay_out = p.pay.out;
+    a.pay_es = p.pay.es;
+    a.has_pay = p.pay.channels > 0;
+    a.perm_out = p.perm_out;
+    a.num_tiles = p.num_tiles;
+    a.num_classes = p.num_classes;
+    a.nbits = p.nbits;
+    a.validate = p.validate;
+    a.err = p.err;
+    const int64_t* o = p.offsets;
+    if (max_len <= 1024) return launch_split<4, 1024>(a, o, s);
+    if (max_len <= 2048) return launch_split<4, 2048>(a, o, s);
     if (max_len <= 4096) {
         switch (g_part_nw4096) {
-            case 1: return launch_split<1, 4096>(a, s);
-            case 2: return launch_split<2, 4096>(a, s);
-            case 4: return launch_split<4, 4096>(a, s);
-            case 16: return launch_split<16, 4096>(a, s);
-            case 108: return launch_split<8, 4096, 8>(a, s);   // 8 waves, 4 workgroups per CU
-            case 104: return launch_split<4, 4096, 4>(a, s);   // 4 waves, 4 workgroups per CU
-            default: return launch_split<8, 4096>(a, s);
+            case 1: return launch_split<1, 4096>(a, o, s);
+            case 2: return launch_split<2, 4096>(a, o, s);
+            case 4: return launch_split<4, 4096>(a, o, s);
+            case 16: return launch_split<16, 4096>(a, o, s);
+            case 108: return launch_split<8, 4096, 8>(a, o, s);   // 8 waves, 4 workgroups per CU
+            case 104: return launch_split<4, 4096, 4>(a, o, s);   // 4 waves, 4 workgroups per CU
+            default: return launch_split<8, 4096>(a, o, s);
         }
     }
-    if (max_len <= 8192) return launch_split<8, 8192>(a, s);
-    return launch_split<16, 16384>(a, s);
+    if (max_len <= 8192) return launch_split<8, 8192>(a, o, s);
+    return launch_split<16, 16384>(a, o, s);
+}
+
+hipError_t launch_sort_split(const SortArgs& q, int64_t max_len, hipStream_t s) {
+    if (q.num_tiles == 0) return hipSuccess;
+    SplitArgs a{};
+    a.keys_in = q.keys_in;
+    a.keys_out = q.keys_out;
+    a.perm_out = q.perm_out;
+    a.num_tiles = q.num_tiles;
+    a.nbits = 32;
+    a.f32 = q.f32;
+    a.err = q.err;
+    const int64_t* o = q.offsets;
+    if (max_len <= 1024) return launch_split<4, 1024, 0, 1>(a, o, s);
+    if (max_len <= 2048) return launch_split<4, 2048, 0, 1>(a, o, s);
+    if (max_len <= 4096) return launch_split<8, 4096, 0, 1>(a, o, s);
+    if (max_len <= 8192) return launch_split<8, 8192, 0, 1>(a, o, s);
+    return launch_split<16, 16384, 0, 1>(a, o, s);
 }
 
 }  // namespace ts
