@@ -4,8 +4,10 @@ Afshani & Sitchinava, "Sorting and Permuting without Bank Conflicts on GPUs".
 The computation lives in the HIP library ``libtilesort.so`` (C interface in
 ``include/tilesort.h``); this package is its Python binding.
 """
+from .autograd import Permute, SortWithPayload, permute, sort_with_payload
 from .ops import (check_device_errors, copy, lds_probe, tile_partition, tile_permute, tile_sort,
                   tune, workspace)
 
 __all__ = ["tile_sort", "tile_partition", "tile_permute", "copy", "lds_probe", "workspace",
-           "check_device_errors", "tune"]
+           "check_device_errors", "tune", "Permute", "SortWithPayload", "permute",
+           "sort_with_payload"]

@@ -1,0 +1,61 @@
+"""Differentiable sort-with-payload and permutation (torch.autograd.Function).
+
+Both backward passes move the upstream gradient through the inverse of the
+forward permutation with the same conflict-free tile kernels; indices and keys
+stay exact integers throughout.
+
+* ``Permute``:  y = scatter(x, pi), i.e. y[pi[i]] = x[i]; dx[i] = dy[pi[i]] (gather).
+* ``SortWithPayload``: keys are fp32, sorted ascending through the order-preserving
+  bit map (stable; -0 before +0); payload_out[:, k] = payload[:, perm[k]] and
+  sorted_keys[k] = keys[perm[k]]; backward scatters: dp[:, perm[k]] = dpo[:, k].
+"""
+from __future__ import annotations
+
+import torch
+
+from . import ops
+
+
+class Permute(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, pi, offsets, max_tile_len=None):
+        y = ops.tile_permute(x.contiguous(), pi, "scatter", offsets, max_tile_len)
+        ctx.save_for_backward(pi, offsets)
+        ctx.max_tile_len = max_tile_len
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        pi, offsets = ctx.saved_tensors
+        gx = ops.tile_permute(gy.contiguous(), pi, "gather", offsets, ctx.max_tile_len)
+        return gx, None, None, None
+
+
+class SortWithPayload(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, keys, payload, offsets, max_tile_len=None):
+        assert keys.dtype == torch.float32, "keys must be float32"
+        k, p, perm = ops.tile_sort(keys.contiguous(), payload.contiguous(), offsets,
+                                   max_tile_len=max_tile_len, f32_ordered=True, want_perm=True)
+        ctx.save_for_backward(perm, offsets)
+        ctx.max_tile_len = max_tile_len
+        ctx.mark_non_differentiable(perm)
+        return k, p, perm
+
+    @staticmethod
+    def backward(ctx, g_keys, g_payload, g_perm):
+        perm, offsets = ctx.saved_tensors
+        gk = gp = None
+        if g_keys is not None and ctx.needs_input_grad[0]:
+            gk = ops.tile_permute(g_keys.contiguous(), perm, "scatter", offsets, ctx.max_tile_len)
+        if g_payload is not None and ctx.needs_input_grad[1]:
+            gp = ops.tile_permute(g_payload.contiguous(), perm, "scatter", offsets, ctx.max_tile_len)
+        return gk, gp, None, None
+
+
+def permute(x, pi, offsets, max_tile_len=None):
+    return Permute.apply(x, pi, offsets, max_tile_len)
+
+
+def sort_with_payload(keys, payload, offsets, max_tile_len=None):
+    return SortWithPayload.apply(keys, payload, offsets, max_tile_len)

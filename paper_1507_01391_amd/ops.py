@@ -15,6 +15,7 @@ import torch
 from . import _lib
 
 _WORDS = (torch.int32, torch.float32, torch.uint32)
+_DWORDS = (torch.float64, torch.int64)  # moved as two 32-bit words per element
 _workspaces: dict = {}
 
 
@@ -46,10 +47,10 @@ def check_device_errors(device=None) -> None:
     _lib.check(_lib.load().ts_check(_ptr(ws), _stream(ws.device)))
 
 
-def _as_words(t: torch.Tensor, name: str) -> torch.Tensor:
+def _as_words(t: torch.Tensor, name: str, allow_64: bool = False) -> torch.Tensor:
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor")
-    if t.dtype not in _WORDS:
+    if t.dtype not in _WORDS and not (allow_64 and t.dtype in _DWORDS):
         raise TypeError(f"{name}: 32-bit dtype required, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
@@ -57,9 +58,17 @@ def _as_words(t: torch.Tensor, name: str) -> torch.Tensor:
 
 
 def _payload_layout(payload: Optional[torch.Tensor], n: int):
-    """payload: None, [N] (one channel) or [C, N] channel-planar.  Returns (channels, es, cs)."""
+    """payload: None, [N] (one channel) or [C, N] channel-planar; 64-bit dtypes are moved
+    as two 32-bit words per element.  Returns (channels, es, cs) in 32-bit words."""
     if payload is None:
         return 0, 1, 0
+    if payload.dtype in _DWORDS:
+        if payload.dim() == 1:
+            assert payload.shape[0] == n
+            return 2, 2, 1                      # [N, 2] words, array of structs
+        assert payload.dim() == 2 and payload.shape[1] == n
+        # [C, N] of 64-bit: word (g, c, h) at c*2N + 2g + h -> only one channel group per call
+        raise ValueError("64-bit payloads must be 1-D")
     if payload.dim() == 1:
         assert payload.shape[0] == n, "payload length must match keys"
         return 1, 1, 0
@@ -120,7 +129,7 @@ def tile_permute(x: torch.Tensor, pi: torch.Tensor, direction: str = "scatter", 
                  validate: bool = False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Apply tile-local permutations: scatter out[pi[i]] = x[i], gather out[i] = x[pi[i]].
     ``x`` is [N] or [C, N] (channel-planar)."""
-    x = _as_words(x, "x")
+    x = _as_words(x, "x", allow_64=True)
     n = x.shape[-1]
     dev = x.device
     assert pi.dtype == torch.int32 and pi.shape[0] == n and pi.is_cuda
@@ -151,7 +160,7 @@ def tile_sort(keys: torch.Tensor, payload: Optional[torch.Tensor] = None, offset
     off = _offsets(offsets, n, dev)
     ch, es, cs = _payload_layout(payload, n)
     if payload is not None:
-        payload = _as_words(payload, "payload")
+        payload = _as_words(payload, "payload", allow_64=True)
         if payload_out is None:
             payload_out = torch.empty_like(payload)
     if keys_out is None:
