@@ -179,7 +179,11 @@ ts_status ts_lds_probe(const uint32_t* lane_words, int op, int width, int iters,
 
 /* Override a tuning knob of the kernel-selection table (used by the autotuner).
    Knobs: "partition_waves_4096" (1, 2, 4, 8 or 16 waves per workgroup; 104 and 108:
-   4 or 8 waves with registers capped so four workgroups fit on a CU).
+   4 or 8 waves with registers capped so four workgroups fit on a CU; 118: 8 waves
+   without prefetching the next tile; 204, 208, 216:
+   two tiles per workgroup with 4, 8 or 16 waves); "permute_variant" (0: registers as
+   the compiler chooses; 1: registers capped for more workgroups per CU; 2: 8-wave
+   workgroups for 8192-item tiles).
    Returns TS_ERR_INVALID for an unknown knob or value. */
 ts_status ts_tune(const char* knob, int value);
 

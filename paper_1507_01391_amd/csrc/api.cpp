@@ -283,10 +283,17 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
 ts_status ts_tune(const char* knob, int value) {
     if (knob == nullptr) return fail(TS_ERR_INVALID, "ts_tune: knob is NULL");
     if (std::strcmp(knob, "partition_waves_4096") == 0) {
-        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16 && value != 104 &&
-            value != 108)
-            return fail(TS_ERR_INVALID, "ts_tune: partition_waves_4096 must be 1, 2, 4, 8, 16, 104 or 108");
+        static const int ok[] = {1, 2, 4, 8, 16, 104, 106, 108, 118, 204, 208, 216};
+        bool found = false;
+        for (int v : ok) found |= (v == value);
+        if (!found)
+            return fail(TS_ERR_INVALID, "ts_tune: partition_waves_4096 must be one of 1, 2, 4, 8, 16, 104, 106, 108, 118, 204, 208, 216");
         ts::set_partition_waves(value);
+        return TS_OK;
+    }
+    if (std::strcmp(knob, "permute_variant") == 0) {
+        if (value < 0 || value > 2) return fail(TS_ERR_INVALID, "ts_tune: permute_variant must be 0, 1 or 2");
+        ts::set_permute_variant(value);
         return TS_OK;
     }
     return fail(TS_ERR_INVALID, "ts_tune: unknown knob '%s'", knob);

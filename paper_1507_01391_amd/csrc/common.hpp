@@ -48,28 +48,29 @@ TS_DEV uint32_t select_by_mask(uint64_t mask, uint32_t if0, uint32_t if1) {
 }
 
 // Issue CPW coalesced 32-bit global loads of one tile, column j = items 64*(c0+j) + lane,
-// with no waits between them: lanes past the end of the tile read item 0 instead (valid
-// for n > 0) and the caller replaces those values.  Element g of the tile is at
-// base[(o + g) * stride].  Unit stride uses a wave-uniform tile pointer and 32-bit lane
-// offsets (scalar-base addressing); other strides use 64-bit addresses.
+// with no waits between them and no branches around them.  Element g of the tile is at
+// base[(o + g) * stride].  Lanes past the end (and every lane when n <= 0) read from
+// `fallback` -- any always-readable address -- and the caller ignores those values.
+// Unit stride uses a wave-uniform tile pointer and 32-bit byte offsets (scalar-base
+// addressing); other strides use 64-bit addresses.
 template <int CPW, typename T>
 TS_DEV void load_columns(const T* __restrict__ base, int64_t stride, int64_t o, int n, int c0,
-                         int lane, T (&out)[CPW]) {
+                         int lane, T (&out)[CPW], const void* fallback) {
+    const bool any = n > 0;
     if (stride == 1) {
-        // 32-bit byte offsets from a uniform pointer: scalar-base (saddr) global loads
-        const char* tb = (const char*)(base + o);
+        const char* tb = any ? (const char*)(base + o) : (const char*)fallback;
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
             const uint32_t i = (uint32_t)(64 * (c0 + j) + lane);
-            const uint32_t off = ((i < (uint32_t)n) ? i : 0u) * (uint32_t)sizeof(T);
+            const uint32_t off = (i < (uint32_t)n) ? i * (uint32_t)sizeof(T) : 0u;
             out[j] = *(const T*)(tb + off);
         }
     } else {
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
             const int i = 64 * (c0 + j) + lane;
-            const int ii = (i < n) ? i : 0;
-            out[j] = base[(o + ii) * stride];
+            const T* p = (i < n) ? base + (o + i) * stride : (const T*)fallback;
+            out[j] = *p;
         }
     }
 }

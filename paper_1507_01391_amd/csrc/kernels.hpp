@@ -71,6 +71,7 @@ hipError_t launch_sort_naive(const SortArgs& a, int64_t max_len, hipStream_t s);
 
 int64_t partition_split_capacity();
 void set_partition_waves(int nw);
+void set_permute_variant(int v);
 int64_t permute_split_capacity();
 int64_t sort_capacity(int sched);
 

@@ -37,18 +37,14 @@ __global__ __launch_bounds__(NW * 64) void partition_naive_kernel(PartitionArgs 
     int64_t Lo = 0;
     int Ln = -1;
     auto issue = [&](int64_t tt) {
-        if (tt >= a.num_tiles) { Ln = -1; return; }
-        Lo = a.offsets[tt];
-        const int64_t len = a.offsets[tt + 1] - Lo;
-        Ln = (len > CAP) ? -2 : (int)len;
-        if (Ln <= 0) return;
-#pragma unroll
-        for (int j = 0; j < CPW; ++j) {
-            const int i = 64 * (wv * CPW + j) + lane;
-            const int ii = (i < Ln) ? i : 0;
-            Llab[j] = a.labels_in[Lo + ii];
-            Lpay[j] = has_pay ? a.pay.in[(Lo + ii) * a.pay.es] : 0u;
-        }
+        const bool exists = tt < a.num_tiles;
+        const int64_t t0 = exists ? tt : 0;
+        Lo = a.offsets[t0];
+        const int64_t len = a.offsets[t0 + 1] - Lo;
+        Ln = !exists ? -1 : ((len > CAP) ? -2 : (int)len);
+        const int nn = (Ln > 0) ? Ln : 0;
+        load_columns<CPW>(a.labels_in, 1, Lo, nn, wv * CPW, lane, Llab, a.offsets);
+        load_columns<CPW>(a.pay.in, a.pay.es, Lo, has_pay ? nn : 0, wv * CPW, lane, Lpay, a.offsets);
     };
     int64_t t = blockIdx.x;
     issue(t);
@@ -153,13 +149,13 @@ __global__ __launch_bounds__(NW * 64) void permute_naive_kernel(PermuteArgs a) {
         }
         const int n = (int)len;
         int32_t pidx[CPW];
-        if (n > 0) load_columns<CPW>(a.pi, 1, o, n, w * CPW, lane, pidx);
+        load_columns<CPW>(a.pi, 1, o, n, w * CPW, lane, pidx, a.offsets);
 #pragma unroll
         for (int j = 0; j < CPW; ++j) pidx[j] &= (CAP - 1);
         for (uint32_t c = 0; c < a.pay.channels; ++c) {
             const int64_t cb = (int64_t)c * a.pay.cs;
             uint32_t xv[CPW];
-            if (n > 0) load_columns<CPW>(a.pay.in + cb, a.pay.es, o, n, w * CPW, lane, xv);
+            load_columns<CPW>(a.pay.in + cb, a.pay.es, o, n, w * CPW, lane, xv, a.offsets);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
                 const int i = 64 * (w * CPW + j) + lane;
@@ -210,7 +206,7 @@ __global__ __launch_bounds__(NW * 64) void sort_naive_kernel(SortArgs a) {
         }
         const int n = (int)len;
         uint32_t kv[CPW];
-        if (n > 0) load_columns<CPW>(a.keys_in, 1, o, n, w * CPW, lane, kv);
+        load_columns<CPW>(a.keys_in, 1, o, n, w * CPW, lane, kv, a.offsets);
         uint64_t e[CPW];
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {

@@ -64,17 +64,17 @@ struct TileLoad {
 template <int CPW, int CAP>
 TS_DEV void issue_tile_load(const SplitArgs& a, const int64_t* __restrict__ offs, int64_t t,
                             int w, int lane, TileLoad<CPW>& L) {
-    if (t >= a.num_tiles) {
-        L.n = -1;
-        return;
-    }
-    const int64_t o = offs[t];
-    const int64_t len = offs[t + 1] - o;
+    // Branch-free: an absent tile reads the offsets of tile 0 and loads nothing useful,
+    // so the previous contents of L never have to be kept alive.
+    const bool exists = t < a.num_tiles;
+    const int64_t tt = exists ? t : 0;
+    const int64_t o = offs[tt];
+    const int64_t len = offs[tt + 1] - o;
     L.o = o;
-    L.n = (len > CAP) ? -2 : (int)len;
-    if (L.n <= 0) return;
-    load_columns<CPW>(a.keys_in, 1, o, L.n, w * CPW, lane, L.lab);
-    if (a.has_pay) load_columns<CPW>(a.pay_in, a.pay_es, o, L.n, w * CPW, lane, L.pay);
+    L.n = !exists ? -1 : ((len > CAP) ? -2 : (int)len);
+    const int nn = (L.n > 0) ? L.n : 0;
+    load_columns<CPW>(a.keys_in, 1, o, nn, w * CPW, lane, L.lab, offs);
+    load_columns<CPW>(a.pay_in, a.pay_es, o, a.has_pay ? nn : 0, w * CPW, lane, L.pay, offs);
 }
 
 template <int NW, int CAP, int WPE, int MODE>
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0
 void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
     constexpr int CPW = CAP / 64 / NW;  // columns per wave
     // Narrow waves have room to load the next tile during this one; wide ones load
-    // each tile when they start it.
+    // each tile when they start it (WPE < 0: never prefetch).
     constexpr bool PREFETCH = CPW <= 16 && WPE == 0;
     __shared__ uint64_t A[CAP];
     __shared__ int wz[NW];
@@ -100,8 +100,7 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
         const int n = L.n;
         if (n == -2) {  // longer than this kernel's capacity: skip and flag
             if (threadIdx.x == 0) atomicOr(a.err, ERR_TILE_TOO_LONG);
-            if (PREFETCH) issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
-            else if (t + gridDim.x < a.num_tiles) issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
+            issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
             continue;
         }
         // The tile is padded to the kernel capacity: every wave always owns CPW full
@@ -215,6 +214,164 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
     }
 }
 
+// Two tiles per workgroup in lockstep: every barrier of a pass serves both tiles, so
+// the per-tile synchronisation cost halves and each wave can keep twice the items in
+// registers (the workgroup holds 2 x CAP items of LDS).  Same splits as split_kernel.
+template <int NW, int CAP, int MODE>
+__global__ __launch_bounds__(NW * 64) void split2_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
+    constexpr int CPW = CAP / 64 / NW;
+    constexpr int N = CAP;
+    constexpr bool PREFETCH = CPW <= 8;
+    __shared__ uint64_t A[2][CAP];
+    __shared__ int wz[2][NW];
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lmask = (MODE == 0) ? (1u << a.nbits) - 1u : 0xFFFFFFFFu;
+    const bool has_pay = a.has_pay != 0;
+    const int64_t pairs = (a.num_tiles + 1) / 2;
+
+    TileLoad<CPW> L[2];
+    int64_t g = blockIdx.x;
+    issue_tile_load<CPW, CAP>(a, offs, 2 * g, w, lane, L[0]);
+    issue_tile_load<CPW, CAP>(a, offs, 2 * g + 1, w, lane, L[1]);
+
+    for (; g < pairs; g += gridDim.x) {
+        int64_t o[2];
+        int n[2];
+        uint64_t e[2][CPW];
+        bool bad = false;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            o[tt] = L[tt].o;
+            n[tt] = L[tt].n;
+            if (n[tt] == -2) {
+                if (threadIdx.x == 0) atomicOr(a.err, ERR_TILE_TOO_LONG);
+                n[tt] = -1;  // skipped: nothing is stored
+            }
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int i = 64 * (w * CPW + j) + lane;
+                uint32_t lab = lmask, pay = 0;
+                if (i < n[tt]) {
+                    lab = L[tt].lab[j];
+                    if (MODE == 0) {
+                        bad |= lab >= a.num_classes;
+                        lab &= lmask;
+                        pay = L[tt].pay[j];
+                    } else if (a.f32) {
+                        lab = f32_to_ordered(lab);
+                    }
+                }
+                e[tt][j] = (MODE == 0) ? pack(((uint32_t)i << 16) | lab, pay) : pack(lab, (uint32_t)i);
+            }
+        }
+        if (a.validate) flag_error(a.err, bad, ERR_BAD_LABEL);
+        if (PREFETCH) {
+            issue_tile_load<CPW, CAP>(a, offs, 2 * (g + gridDim.x), w, lane, L[0]);
+            issue_tile_load<CPW, CAP>(a, offs, 2 * (g + gridDim.x) + 1, w, lane, L[1]);
+        }
+
+        const uint32_t lane8 = (uint32_t)lane * 8u;
+        const uint32_t neg_lane8 = 0u - lane8;
+        const uint32_t fwd_base = lane8 + (uint32_t)(w * CPW * 512);
+        for (int b = 0; b < a.nbits; ++b) {
+            int zc[2] = {0, 0};
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) zc[tt] += 64 - popc64(ballot((hi32(e[tt][j]) >> b) & 1u));
+            if (lane == 0) {
+                wz[0][w] = zc[0];
+                wz[1][w] = zc[1];
+            }
+            __syncthreads();  // every wave has read the previous pass and posted its counts
+            int zb[2] = {0, 0}, zt[2] = {0, 0};
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                const int mine = (lane < NW) ? wz[tt][lane] : 0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const int v = __builtin_amdgcn_readlane(mine, q);
+                    zt[tt] += v;
+                    zb[tt] += (q < w) ? v : 0;
+                }
+            }
+            bool run[2];
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                // nothing to do for an absent tile, or when every item has the same bit
+                run[tt] = n[tt] > 0 && !(MODE == 1 && (zt[tt] == 0 || zt[tt] == N));
+                if (!run[tt]) continue;
+                int z = zb[tt];
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) {
+                    const int k = w * CPW + j;
+                    const uint64_t bj = ballot((hi32(e[tt][j]) >> b) & 1u);
+                    const uint32_t r0 = count_below(~bj);
+                    const uint32_t z8 = (uint32_t)__builtin_amdgcn_readfirstlane(z * 8);
+                    const uint32_t o8 = (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 - 64 * k + z) * 8);
+                    const uint32_t a0 = r0 * 8u + z8;
+                    const uint32_t a1 = (r0 * 8u + neg_lane8) + o8;
+                    lds_store(A[tt], select_by_mask(bj, a0, a1), e[tt][j]);
+                    z += 64 - popc64(bj);
+                }
+            }
+            __syncthreads();  // both split tiles are complete
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                if (!run[tt]) continue;
+                const int ztt = zt[tt];
+                const uint32_t rev_base =
+                    (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 + ztt - 64 * w * CPW - 64 * (CPW - 1)) * 8) +
+                    neg_lane8;
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) {
+                    const int base = 64 * (w * CPW + j);
+                    if (base + 64 <= ztt) {
+                        e[tt][j] = lds_load(A[tt], fwd_base + 512u * j);
+                    } else if (base >= ztt) {
+                        e[tt][j] = lds_load(A[tt], rev_base + 512u * (CPW - 1 - j));
+                    } else {
+                        e[tt][j] = lds_load(A[tt], (lane < ztt - base) ? fwd_base + 512u * j
+                                                                   : rev_base + 512u * (CPW - 1 - j));
+                    }
+                }
+            }
+        }
+
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int v = 64 * (w * CPW + j) + lane;
+                if (v < n[tt]) {
+                    const uint32_t h = hi32(e[tt][j]);
+                    if (MODE == 0) {
+                        if (a.keys_out) store_item(a.keys_out, 1, o[tt], v, h & 0xFFFFu);
+                        if (has_pay) store_item(a.pay_out, a.pay_es, o[tt], v, lo32(e[tt][j]));
+                        if (a.perm_out) store_item(a.perm_out, 1, o[tt], v, (int32_t)(h >> 16));
+                    } else {
+                        if (a.keys_out) store_item(a.keys_out, 1, o[tt], v, a.f32 ? ordered_to_f32(h) : h);
+                        if (a.perm_out) store_item(a.perm_out, 1, o[tt], v, (int32_t)lo32(e[tt][j]));
+                    }
+                }
+            }
+        }
+        if (!PREFETCH) {
+            issue_tile_load<CPW, CAP>(a, offs, 2 * (g + gridDim.x), w, lane, L[0]);
+            issue_tile_load<CPW, CAP>(a, offs, 2 * (g + gridDim.x) + 1, w, lane, L[1]);
+        }
+    }
+}
+
+template <int NW, int CAP, int MODE>
+hipError_t launch_split2(const SplitArgs& a, const int64_t* offs, hipStream_t s) {
+    auto kern = split2_kernel<NW, CAP, MODE>;
+    const int grid = persistent_grid((const void*)kern, NW * 64, 0, (a.num_tiles + 1) / 2);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, offs);
+    return hipGetLastError();
+}
+
 template <int NW, int CAP, int WPE = 0, int MODE = 0>
 hipError_t launch_split(const SplitArgs& a, const int64_t* offs, hipStream_t s) {
     auto kern = split_kernel<NW, CAP, WPE, MODE>;
@@ -227,8 +384,9 @@ hipError_t launch_split(const SplitArgs& a, const int64_t* offs, hipStream_t s) 
 
 int64_t partition_split_capacity() { return 16384; }
 
-// Wave count per workgroup for the 4096-item kernel (tuning knob, see the plan table).
-static int g_part_nw4096 = 8;
+// Kernel variant for 4096-item tiles (tuning knob): wave count, or 1xx = 8/4 waves with
+// a register cap; the default fits three workgroups per CU.
+static int g_part_nw4096 = 106;
 void set_partition_waves(int nw) { g_part_nw4096 = nw; }
 
 hipError_t launch_partition_split(const PartitionArgs& p, int64_t max_len, hipStream_t s) {
@@ -257,6 +415,11 @@ hipError_t launch_partition_split(const PartitionArgs& p, int64_t max_len, hipSt
             case 16: return launch_split<16, 4096>(a, o, s);
             case 108: return launch_split<8, 4096, 8>(a, o, s);   // 8 waves, 4 workgroups per CU
             case 104: return launch_split<4, 4096, 4>(a, o, s);   // 4 waves, 4 workgroups per CU
+            case 118: return launch_split<8, 4096, -1>(a, o, s);  // 8 waves, no prefetch
+            case 106: return launch_split<8, 4096, 6>(a, o, s);   // 8 waves, three workgroups per CU
+            case 208: return launch_split2<8, 4096, 0>(a, o, s);  // two tiles per workgroup
+            case 204: return launch_split2<4, 4096, 0>(a, o, s);
+            case 216: return launch_split2<16, 4096, 0>(a, o, s);
             default: return launch_split<8, 4096>(a, o, s);
         }
     }

@@ -14,9 +14,9 @@ namespace ts {
 
 namespace {
 
-template <int NW, int CAP, bool GATHER>
-__global__ __launch_bounds__(NW * 64) void permute_split_kernel(PermuteArgs a,
-                                                               const int64_t* __restrict__ offs) {
+template <int NW, int CAP, bool GATHER, int WPE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
     using R = Router<NW, CAP>;
     constexpr int CPW = R::CPW;
     __shared__ uint64_t A[CAP];
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(NW * 64) void permute_split_kernel(PermuteArgs a,
         uint32_t dst[CPW];
         bool bad = false;
         int32_t piv[CPW];
-        if (n > 0) load_columns<CPW>(a.pi, 1, o, n, w * CPW, lane, piv);
+        load_columns<CPW>(a.pi, 1, o, n, w * CPW, lane, piv, offs);
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
             const int i = 64 * (w * CPW + j) + lane;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(NW * 64) void permute_split_kernel(PermuteArgs a,
         for (uint32_t c = 0; c < a.pay.channels; ++c) {
             const int64_t cbase = (int64_t)c * a.pay.cs;
             uint32_t xv[CPW];
-            if (n > 0) load_columns<CPW>(a.pay.in + cbase, a.pay.es, o, n, w * CPW, lane, xv);
+            load_columns<CPW>(a.pay.in + cbase, a.pay.es, o, n, w * CPW, lane, xv, offs);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) e[j] = pack(dst[j], xv[j]);
             R::route(A, wz, e, w, lane);
@@ -91,10 +91,10 @@ __global__ __launch_bounds__(NW * 64) void permute_split_kernel(PermuteArgs a,
     }
 }
 
-template <int NW, int CAP>
+template <int NW, int CAP, int WPE = 0>
 hipError_t launch_perm(const PermuteArgs& a, hipStream_t s) {
-    auto kern = (a.direction == 1) ? permute_split_kernel<NW, CAP, true>
-                                   : permute_split_kernel<NW, CAP, false>;
+    auto kern = (a.direction == 1) ? permute_split_kernel<NW, CAP, true, WPE>
+                                   : permute_split_kernel<NW, CAP, false, WPE>;
     const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, a.offsets);
     return hipGetLastError();
@@ -104,10 +104,19 @@ hipError_t launch_perm(const PermuteArgs& a, hipStream_t s) {
 
 int64_t permute_split_capacity() { return 16384; }
 
+// Kernel variant for 8192-item tiles (tuning knob): 0 = 16 waves, registers as the
+// compiler likes; 1 = 16 waves capped at 64 registers (two workgroups per CU).
+static int g_perm_variant = 0;
+void set_permute_variant(int v) { g_perm_variant = v; }
+
 hipError_t launch_permute_split(const PermuteArgs& a, int64_t max_len, hipStream_t s) {
     if (a.num_tiles == 0) return hipSuccess;
-    if (max_len <= 4096) return launch_perm<8, 4096>(a, s);
-    if (max_len <= 8192) return launch_perm<16, 8192>(a, s);
+    if (max_len <= 4096) return g_perm_variant == 1 ? launch_perm<8, 4096, 6>(a, s) : launch_perm<8, 4096>(a, s);
+    if (max_len <= 8192) {
+        if (g_perm_variant == 1) return launch_perm<16, 8192, 8>(a, s);
+        if (g_perm_variant == 2) return launch_perm<8, 8192>(a, s);
+        return launch_perm<16, 8192>(a, s);
+    }
     return launch_perm<16, 16384>(a, s);
 }
 

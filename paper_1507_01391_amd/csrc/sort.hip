@@ -183,18 +183,12 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         // ---- load: register c, lane L = item 64c + L (coalesced); padding sorts last
         uint64_t v[R];
         {
-            const char* kb = (const char*)(a.keys_in + o);
+            uint32_t kk[R];
+            load_columns<R>(a.keys_in, 1, o, n, 0, lane, kk, offs);
 #pragma unroll
             for (int c = 0; c < R; ++c) {
                 const uint32_t i = (uint32_t)(64 * c + lane);
-                const uint32_t key = (n > 0) ? *(const uint32_t*)(kb + ((i < (uint32_t)n) ? i : 0u) * 4u) : 0u;
-                v[c] = pack(key, i);
-            }
-#pragma unroll
-            for (int c = 0; c < R; ++c) {
-                const uint32_t i = (uint32_t)(64 * c + lane);
-                uint32_t key = hi32(v[c]);
-                key = (i < (uint32_t)n) ? (a.f32 ? f32_to_ordered(key) : key) : 0xFFFFFFFFu;
+                const uint32_t key = (i < (uint32_t)n) ? (a.f32 ? f32_to_ordered(kk[c]) : kk[c]) : 0xFFFFFFFFu;
                 v[c] = pack(key, i);
             }
         }
