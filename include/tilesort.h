@@ -86,6 +86,9 @@ enum {
     TS_SCHED_THM2 = 2,    /* the paper's Theorem 2 schedule: Lemma 1 on super-rows,
                              column sorts, row sorts (sort and partition) */
     TS_SCHED_BITONIC = 3, /* register row sorts + conflict-free transposes (sort) */
+    TS_SCHED_MERGE = 4,   /* sort of uneven tiles up to 2^20 keys: short tiles packed up to
+                             eight per wavefront, long tiles cut into 4096-key pieces sorted
+                             like BITONIC, then rounds of pairwise bitonic merges (sort) */
     TS_SCHED_NAIVE = 15   /* baseline: plain LDS counting / direct scatter, with bank
                              conflicts (all three ops) */
 };
@@ -101,14 +104,21 @@ enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2 };
  *   payload_in / out    : optional (channels may be 0; pointers may then be NULL);
  *                         payload_out[k] = payload_in[source of k].
  *   perm_out            : optional int32 [N]: tile-local source index of slot k.
- * Supported tile length: max_tile_len <= 16384 for the single-tile schedules;
- * longer tiles return TS_ERR_UNSUPPORTED.
+ *   total_len           : N = tile_offsets[num_tiles], the length of the flat arrays;
+ *                         the merge schedule places its runs in the workspace by it,
+ *                         and skips (and flags) a tile outside [0, N).
+ * Supported tile length: 4096 for THM2 and BITONIC, 16384 for SPLIT and NAIVE,
+ * 2^20 for MERGE; a longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the
+ * autotuned plan for max_tile_len up to 4096 / 8192 / 16384 and MERGE beyond.
+ * The workspace must hold ts_workspace_bytes(TS_OP_SORT, flags, ...) bytes: the
+ * merge schedule needs about 16 bytes per key for its runs and work lists.
  */
 ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out,
                     const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
                     int64_t elem_stride, int64_t chan_stride, int32_t* perm_out,
-                    const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
-                    uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+                    const int64_t* tile_offsets, int64_t num_tiles, int64_t total_len,
+                    int64_t max_tile_len, uint32_t flags, void* workspace,
+                    size_t workspace_bytes, void* stream);
 
 /*
  * tile_partition -- w-way partition (Sec. 1: an item with label i is sent to row i;
@@ -139,8 +149,10 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels,
                        const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
                        uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
 
-/* Bytes of workspace the given call needs (never 0). */
-size_t ts_workspace_bytes(int op, int64_t num_tiles, int64_t max_tile_len, uint32_t channels);
+/* Bytes of workspace a call of operation `op` (TS_OP_*) with these flags and sizes
+   needs (never 0).  total_len is the number of items (tile_offsets[num_tiles]). */
+size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t total_len,
+                          int64_t max_tile_len, uint32_t channels);
 
 /* Zero a workspace (its error word and counters) on `stream`.  Call once after
    allocating it. */
@@ -183,7 +195,10 @@ ts_status ts_lds_probe(const uint32_t* lane_words, int op, int width, int iters,
    without prefetching the next tile; 204, 208, 216:
    two tiles per workgroup with 4, 8 or 16 waves); "permute_variant" (0: registers as
    the compiler chooses; 1: registers capped for more workgroups per CU; 2: 8-wave
-   workgroups for 8192-item tiles).
+   workgroups for 8192-item tiles); "merge_pack" (1: tiles of up to 2048 keys share a
+   wavefront in the merge schedule, 0: one tile per wavefront); "sort_plan_4096",
+   "sort_plan_8192", "sort_plan_16384" (the TS_SCHED_* value that tile_sort's AUTO
+   uses for max_tile_len up to that length).
    Returns TS_ERR_INVALID for an unknown knob or value. */
 ts_status ts_tune(const char* knob, int value);
 

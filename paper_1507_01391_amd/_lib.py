@@ -15,7 +15,7 @@ TS_OK, TS_ERR_INVALID, TS_ERR_UNSUPPORTED, TS_ERR_HIP, TS_ERR_WORKSPACE = range(
 TS_SCATTER, TS_GATHER = 0, 1
 TS_FLAG_F32_ORDERED = 1
 TS_FLAG_VALIDATE = 2
-SCHED = {"auto": 0, "split": 1, "thm2": 2, "bitonic": 3, "naive": 15}
+SCHED = {"auto": 0, "split": 1, "thm2": 2, "bitonic": 3, "merge": 4, "naive": 15}
 TS_OP_SORT, TS_OP_PARTITION, TS_OP_PERMUTE = 0, 1, 2
 
 # Every symbol include/tilesort.h declares.
@@ -49,12 +49,12 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     P, I64, U32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
     S = ctypes.c_int
-    lib.tile_sort.argtypes = [P, P, P, P, U32, I64, I64, P, P, I64, I64, U32, P, SZ, P]
+    lib.tile_sort.argtypes = [P, P, P, P, U32, I64, I64, P, P, I64, I64, I64, U32, P, SZ, P]
     lib.tile_partition.argtypes = [P, P, P, P, U32, I64, I64, U32, P, P, I64, I64, U32, P, SZ, P]
     lib.tile_permute.argtypes = [P, P, U32, I64, I64, P, U32, P, I64, I64, U32, P, SZ, P]
     for f in ("tile_sort", "tile_partition", "tile_permute"):
         getattr(lib, f).restype = S
-    lib.ts_workspace_bytes.argtypes = [ctypes.c_int, I64, I64, U32]
+    lib.ts_workspace_bytes.argtypes = [ctypes.c_int, U32, I64, I64, I64, U32]
     lib.ts_workspace_bytes.restype = SZ
     lib.ts_workspace_init.argtypes = [P, SZ, P]
     lib.ts_workspace_init.restype = S

@@ -37,6 +37,20 @@ constexpr size_t kWorkspaceBytes = 256;
 
 int sched_of(uint32_t flags) { return (int)((flags >> 8) & 0xFu); }
 
+// Schedules TS_SCHED_AUTO picks for tile_sort, by max_tile_len up to 4096, 8192 and
+// 16384 (longer tiles always take the merge schedule).  Set by the autotuner through
+// ts_tune("sort_plan_<len>", schedule).
+int g_sort_plan[3] = {TS_SCHED_BITONIC, TS_SCHED_SPLIT, TS_SCHED_SPLIT};
+
+int resolve_sort_sched(uint32_t flags, int64_t max_len) {
+    const int s = sched_of(flags);
+    if (s != TS_SCHED_AUTO) return s;
+    if (max_len <= 4096) return g_sort_plan[0];
+    if (max_len <= 8192) return g_sort_plan[1];
+    if (max_len <= 16384) return g_sort_plan[2];
+    return TS_SCHED_MERGE;
+}
+
 int bits_for(uint32_t classes) {
     int b = 0;
     while ((1u << b) < classes) ++b;
@@ -111,10 +125,13 @@ const char* ts_last_error(void) { return g_last_error.c_str(); }
 
 const char* ts_version(void) { return "tilesort 0.1 (gfx950)"; }
 
-size_t ts_workspace_bytes(int op, int64_t num_tiles, int64_t max_tile_len, uint32_t channels) {
-    // tile_sort with a payload and no perm_out keeps the permutation in the workspace
-    if (op == TS_OP_SORT && channels > 0 && num_tiles > 0 && max_tile_len > 0)
-        return kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
+size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t total_len,
+                          int64_t max_tile_len, uint32_t channels) {
+    if (op != TS_OP_SORT || num_tiles <= 0 || total_len < 0) return kWorkspaceBytes;
+    const int sched = resolve_sort_sched(flags, max_tile_len);
+    if (sched == TS_SCHED_MERGE) return ts::merge_layout(num_tiles, total_len, max_tile_len).total;
+    // a payload without perm_out keeps the permutation in the workspace
+    if (channels > 0) return kWorkspaceBytes + (size_t)total_len * 4u;
     return kWorkspaceBytes;
 }
 
@@ -138,6 +155,7 @@ ts_status ts_check(void* workspace, void* stream) {
     if (word & ts::ERR_TILE_TOO_LONG) msg += "a tile was longer than the kernel capacity (skipped); ";
     if (word & ts::ERR_BAD_LABEL) msg += "label >= num_classes; ";
     if (word & ts::ERR_BAD_PERM) msg += "pi is not a permutation of its tile; ";
+    if (word & ts::ERR_BAD_OFFSETS) msg += "a tile lies outside [0, total_len) (skipped); ";
     return fail(TS_ERR_INVALID, "device reported: %s", msg.c_str());
 }
 
@@ -223,52 +241,63 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int
 ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* payload_in,
                     uint32_t* payload_out, uint32_t channels, int64_t elem_stride,
                     int64_t chan_stride, int32_t* perm_out, const int64_t* tile_offsets,
-                    int64_t num_tiles, int64_t max_tile_len, uint32_t flags, void* workspace,
-                    size_t workspace_bytes, void* stream) {
+                    int64_t num_tiles, int64_t total_len, int64_t max_tile_len, uint32_t flags,
+                    void* workspace, size_t workspace_bytes, void* stream) {
     ts_status st = check_common(tile_offsets, num_tiles, max_tile_len, workspace, workspace_bytes);
     if (st != TS_OK) return st;
+    if (total_len < 0) return fail(TS_ERR_INVALID, "tile_sort: total_len < 0");
     if (num_tiles > 0 && keys_in == nullptr) return fail(TS_ERR_INVALID, "tile_sort: keys_in is NULL");
     if (keys_in != nullptr && keys_in == keys_out)
         return fail(TS_ERR_INVALID, "tile_sort: keys_in and keys_out alias");
     st = check_payload(payload_in, payload_out, channels, elem_stride, chan_stride, true);
     if (st != TS_OK) return st;
-    int sched = sched_of(flags);
-    if (sched == TS_SCHED_AUTO) sched = (max_tile_len <= 4096) ? TS_SCHED_BITONIC : TS_SCHED_SPLIT;
+    const int sched = resolve_sort_sched(flags, max_tile_len);
     if (sched != TS_SCHED_SPLIT && sched != TS_SCHED_THM2 && sched != TS_SCHED_BITONIC &&
-        sched != TS_SCHED_NAIVE)
+        sched != TS_SCHED_MERGE && sched != TS_SCHED_NAIVE)
         return fail(TS_ERR_UNSUPPORTED, "tile_sort: schedule %d not available", sched);
-    const int64_t cap = (sched == TS_SCHED_NAIVE) ? 16384 : ts::sort_capacity(sched);
+    const int64_t cap = (sched == TS_SCHED_NAIVE)   ? 16384
+                        : (sched == TS_SCHED_MERGE) ? ts::MERGE_MAX_TILE
+                                                    : ts::sort_capacity(sched);
     if (max_tile_len > cap)
         return fail(TS_ERR_UNSUPPORTED, "tile_sort: max_tile_len %lld > %lld for this schedule",
                     (long long)max_tile_len, (long long)cap);
-    // The payload is moved by a gather through the permutation; without perm_out the
-    // permutation lives in the workspace after the 256-byte header.
-    int32_t* perm = perm_out;
-    if (channels > 0 && perm == nullptr) {
-        const size_t need = kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
-        if (workspace_bytes < need)
-            return fail(TS_ERR_WORKSPACE, "tile_sort: payload without perm_out needs %zu workspace bytes", need);
-        perm = (int32_t*)((char*)workspace + kWorkspaceBytes);
-    }
+    if (num_tiles == 0) return TS_OK;
     ts::SortArgs a{};
     a.keys_in = keys_in;
     a.keys_out = keys_out;
     a.pay = ts::PayloadRef{payload_in, payload_out, channels, elem_stride, chan_stride};
-    a.perm_out = perm;
+    a.perm_out = perm_out;
     a.offsets = tile_offsets;
     a.num_tiles = num_tiles;
     a.f32 = (flags & TS_FLAG_F32_ORDERED) ? 1u : 0u;
     a.err = (uint32_t*)workspace;
     hipStream_t s = (hipStream_t)stream;
+    if (sched == TS_SCHED_MERGE) {
+        // pieces, merge rounds and the payload gather, all inside the workspace
+        const size_t need = ts::merge_layout(num_tiles, total_len, max_tile_len).total;
+        if (workspace_bytes < need)
+            return fail(TS_ERR_WORKSPACE, "tile_sort: the merge schedule needs %zu workspace bytes (got %zu)",
+                        need, workspace_bytes);
+        return hip_status(ts::launch_sort_merge(a, total_len, max_tile_len, workspace, s),
+                          "tile_sort launch");
+    }
+    // The payload is moved by a gather through the permutation; without perm_out the
+    // permutation lives in the workspace after the 256-byte header.
+    if (channels > 0 && a.perm_out == nullptr) {
+        const size_t need = kWorkspaceBytes + (size_t)total_len * 4u;
+        if (workspace_bytes < need)
+            return fail(TS_ERR_WORKSPACE, "tile_sort: payload without perm_out needs %zu workspace bytes", need);
+        a.perm_out = (int32_t*)((char*)workspace + kWorkspaceBytes);
+    }
     hipError_t e = (sched == TS_SCHED_NAIVE) ? ts::launch_sort_naive(a, max_tile_len, s)
                                              : ts::launch_sort(a, max_tile_len, sched, s);
     if (e != hipSuccess) return hip_status(e, "tile_sort launch");
-    if (channels > 0 && num_tiles > 0) {
+    if (channels > 0) {
         // the payload is not part of the composite: gather it by the permutation
         // (a conflict-free routing per tile), or by a direct LDS gather for the baseline
         ts::PermuteArgs p{};
         p.pay = a.pay;
-        p.pi = perm;
+        p.pi = a.perm_out;
         p.direction = TS_GATHER;
         p.offsets = tile_offsets;
         p.num_tiles = num_tiles;
@@ -294,6 +323,20 @@ ts_status ts_tune(const char* knob, int value) {
     if (std::strcmp(knob, "permute_variant") == 0) {
         if (value < 0 || value > 2) return fail(TS_ERR_INVALID, "ts_tune: permute_variant must be 0, 1 or 2");
         ts::set_permute_variant(value);
+        return TS_OK;
+    }
+    if (std::strcmp(knob, "merge_pack") == 0) {
+        if (value != 0 && value != 1) return fail(TS_ERR_INVALID, "ts_tune: merge_pack must be 0 or 1");
+        ts::set_merge_pack(value);
+        return TS_OK;
+    }
+    static const char* plans[3] = {"sort_plan_4096", "sort_plan_8192", "sort_plan_16384"};
+    for (int i = 0; i < 3; ++i) {
+        if (std::strcmp(knob, plans[i]) != 0) continue;
+        const bool ok = value == TS_SCHED_SPLIT || value == TS_SCHED_MERGE || value == TS_SCHED_NAIVE ||
+                        (i == 0 && (value == TS_SCHED_THM2 || value == TS_SCHED_BITONIC));
+        if (!ok) return fail(TS_ERR_INVALID, "ts_tune: %s: schedule %d cannot sort such tiles", knob, value);
+        g_sort_plan[i] = value;
         return TS_OK;
     }
     return fail(TS_ERR_INVALID, "ts_tune: unknown knob '%s'", knob);

@@ -1,0 +1,184 @@
+// Register-resident bitonic building blocks for one wavefront holding 64 x 64 items
+// (lane L, register c), and conflict-free LDS layout moves between such layouts.
+// Used by the tile sort (sort.hip) and the run merge (merge.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace ts {
+namespace bt {
+
+constexpr int R = 64;  // registers (columns) per lane
+
+// Keep the instruction scheduler from interleaving consecutive network stages: each
+// stage rewrites all 64 registers in place, and interleaving keeps old and new copies
+// alive at once (register pressure above 256 and a single wave per SIMD).
+TS_DEV void stage_fence() {}
+
+TS_DEV void cas(uint64_t& a, uint64_t& b) {  // afterwards a <= b
+    // One 64-bit compare into a lane mask and four selects.  (Written with min/max
+    // the compiler emits two compares per pair.)
+    const uint64_t swap = ballot(b < a);
+    const uint32_t alo = lo32(a), ahi = hi32(a), blo = lo32(b), bhi = hi32(b);
+    a = pack(select_by_mask(swap, ahi, bhi), select_by_mask(swap, alo, blo));
+    b = pack(select_by_mask(swap, bhi, ahi), select_by_mask(swap, blo, alo));
+}
+
+// One stage of a bitonic network on the register index: pairs (i, i ^ J); ascending
+// where bit K of i is clear (K = 0: everywhere ascending).  The networks below are
+// spelled out by template recursion so that every register index is a compile-time
+// constant (a partially unrolled loop would index the register array at run time and
+// put it in scratch memory).
+template <int K, int J>
+TS_DEV void net_stage(uint64_t (&v)[R]) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int l = i ^ J;
+        if (l > i) {
+            if (K == 0 || (i & K) == 0) cas(v[i], v[l]);
+            else cas(v[l], v[i]);
+        }
+    }
+}
+
+// Stages J, J/2, .. 1 with direction bit K.
+template <int K, int J>
+TS_DEV void net_stages(uint64_t (&v)[R]) {
+    net_stage<K, J>(v);
+    stage_fence();
+    if constexpr (J > 1) net_stages<K, J / 2>(v);
+}
+
+// Levels K, 2K, .. R of a bitonic sort on the register index.
+template <int K>
+TS_DEV void net_levels(uint64_t (&v)[R]) {
+    net_stages<(K < R ? K : 0), K / 2>(v);
+    if constexpr (K < R) net_levels<2 * K>(v);
+}
+
+// Ascending bitonic sort of the 64 registers of every lane (672 compare-exchanges).
+TS_DEV void row_sort(uint64_t (&v)[R]) { net_levels<2>(v); }
+
+// Ascending bitonic merge of the 64 registers of every lane (stages 32 .. 1).
+TS_DEV void row_merge(uint64_t (&v)[R]) { net_stages<0, R / 2>(v); }
+
+// Stages j = 2^(KB-1) .. 1 of bitonic level 2^KB on the register index, direction
+// given by bit KB of the register index (ascending when clear).
+template <int KB>
+TS_DEV void reg_level_stages(uint64_t (&v)[R]) {
+    net_stages<(KB < 6 ? (1 << KB) : 0), (1 << (KB - 1))>(v);
+}
+
+TS_DEV void xor_all(uint64_t (&v)[R], uint64_t m) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] ^= m;
+}
+
+enum Move : int { MOVE_NONE = 0, MOVE_T = 1, MOVE_RM2CM = 2, MOVE_CM2RM = 3 };
+
+// Destination (lane, register) of register c of lane L, and the slot skew h(c').
+TS_DEV void move_dst(int move, int L, int c, int& Ld, int& cd) {
+    if (move == MOVE_T) {
+        Ld = c;
+        cd = L;
+    } else if (move == MOVE_RM2CM) {  // super-row of 8 rows: row-major p = 64 i + c
+        Ld = (L & ~7) + (c & 7);
+        cd = 8 * (L & 7) + (c >> 3);
+    } else {  // MOVE_CM2RM: column-major p = 8 c + i
+        Ld = (L & ~7) + (c >> 3);
+        cd = 8 * (c & 7) + (L & 7);
+    }
+}
+TS_DEV int move_skew(int move, int cd) {
+    return move == MOVE_T ? cd : (move == MOVE_RM2CM ? (cd >> 3) : (cd & 7));
+}
+
+// Words of the LDS array a layout move needs (16.25 KiB).
+constexpr int MOVE_WORDS = 64 * 65;
+
+// Apply a layout move through the LDS array A (MOVE_WORDS words).  One wave.
+// The 64-bit composites travel as two 32-bit planes (high words, then low words)
+// through the same array, which halves the LDS a wavefront needs.  In every 32-lane
+// phase of every 32-bit write and read the word addresses are distinct modulo 32, so
+// no instruction has a bank conflict:
+//  * the transpose stores (L', c') at word 65 c' + L' (a row pitch of 65 words skews
+//    row c' by c' banks); a lane's 64 writes and 64 reads are then one base address
+//    plus immediate offsets;
+//  * the super-row moves store (L', c') at word 64 c' + ((L' + h(c')) mod 64) with the
+//    per-move skew h of move_skew.
+TS_DEV void layout_move(uint32_t* A, uint64_t (&v)[R], int move, int lane_in) {
+#pragma unroll
+    for (int half = 1; half >= 0; --half) {
+        wave_lds_fence();  // earlier reads of A (other lanes' slots) stay before these writes
+        // a fresh opaque copy per plane: addresses are recomputed next to their use
+        // instead of being kept live across both planes
+        const int lane = (int)opaque((uint32_t)lane_in);
+        if (move == MOVE_T) {
+#pragma unroll
+            for (int c = 0; c < R; ++c)
+                lds_store(A, (uint32_t)(65 * lane + c) * 4u, half ? hi32(v[c]) : lo32(v[c]));
+        } else {
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                int Ld, cd;
+                move_dst(move, lane, c, Ld, cd);
+                const uint32_t slot = (uint32_t)(cd * 64 + ((Ld + move_skew(move, cd)) & 63));
+                lds_store(A, slot * 4u, half ? hi32(v[c]) : lo32(v[c]));
+            }
+        }
+        wave_lds_fence();  // the reads below see every lane's writes
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const uint32_t slot = (move == MOVE_T)
+                                      ? (uint32_t)(65 * c + lane)
+                                      : (uint32_t)(c * 64 + ((lane + move_skew(move, c)) & 63));
+            const uint32_t w = lds_load(A, slot * 4u);
+            v[c] = half ? pack(w, lo32(v[c])) : pack(hi32(v[c]), w);
+        }
+    }
+    wave_lds_fence();  // later writes of A stay after these reads
+}
+
+// Lanes whose bit `b` is set get an all-ones mask (complemented composites sort in
+// the reverse order).
+TS_DEV uint64_t lane_bit_mask(int lane, int b) { return ((lane >> b) & 1) ? ~0ull : 0ull; }
+
+// Level 2^(6+KB) of the bitonic sort below (KB = 1 .. 6).
+template <int KB>
+TS_DEV void bitonic_level(uint32_t* A, uint64_t (&v)[R], int lane) {
+    layout_move(A, v, MOVE_T, lane);  // lane bits become register bits
+    reg_level_stages<KB>(v);
+    layout_move(A, v, MOVE_T, lane);  // back: register bits
+    const uint64_t m = (KB < 6) ? lane_bit_mask(lane, KB) : 0ull;
+    xor_all(v, m);
+    row_merge(v);
+    xor_all(v, m);
+    if constexpr (KB < 6) bitonic_level<KB + 1>(A, v, lane);
+}
+
+// Batcher's bitonic sort of the 4096 composites of one wavefront.  On entry register c
+// of lane L holds any item; on exit register c of lane L holds rank 64 c + L.  Stages
+// on register bits run in registers; stages on lane bits run in registers after a
+// conflict-free transpose through A.
+TS_DEV void bitonic_sort4096(uint32_t* A, uint64_t (&v)[R], int lane) {
+    // levels 2 .. 64: rows (lanes) sorted, odd rows descending
+    xor_all(v, lane_bit_mask(lane, 0));
+    row_sort(v);
+    xor_all(v, lane_bit_mask(lane, 0));
+    bitonic_level<1>(A, v, lane);     // levels 128 .. 4096
+    layout_move(A, v, MOVE_T, lane);  // to store order
+}
+
+// Bitonic merge of one wavefront's 4096 composites.  On entry register c of lane L
+// holds element 64 c + L of a bitonic sequence; on exit it holds rank 64 c + L.
+// Stages 2048 .. 64 compare registers; stages 32 .. 1 compare registers after a
+// transpose.
+TS_DEV void bitonic_merge4096(uint32_t* A, uint64_t (&v)[R], int lane) {
+    row_merge(v);
+    layout_move(A, v, MOVE_T, lane);
+    row_merge(v);
+    layout_move(A, v, MOVE_T, lane);
+}
+
+}  // namespace bt
+}  // namespace ts

@@ -39,6 +39,17 @@ TS_DEV uint32_t opaque(uint32_t v) {
     return v;
 }
 
+// Cross-lane exchange through LDS inside one wavefront.  The LDS executes a
+// wavefront's instructions in order, so no hardware wait is needed; what must be
+// stopped is the compiler moving loads and stores across this point: it reasons per
+// lane, and where it can prove a lane's own later read disjoint from its earlier
+// writes (a fixed transpose, say) it may hoist the read above writes by other lanes.
+TS_DEV void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Per-lane select driven by a wave mask (e.g. a ballot): lane bit set -> if1, else if0.
 // One v_cndmask with the mask as its SGPR-pair condition.
 TS_DEV uint32_t select_by_mask(uint64_t mask, uint32_t if0, uint32_t if1) {

@@ -11,6 +11,7 @@ enum : uint32_t {
     ERR_TILE_TOO_LONG = 1u,   // a tile exceeded the kernel's capacity and was skipped
     ERR_BAD_LABEL = 2u,       // TS_FLAG_VALIDATE: label >= num_classes
     ERR_BAD_PERM = 4u,        // TS_FLAG_VALIDATE: pi is not a permutation of its tile
+    ERR_BAD_OFFSETS = 8u,     // a tile outside [0, total_len) (skipped)
 };
 
 
@@ -55,6 +56,41 @@ struct SortArgs {
     uint32_t f32;       // nonzero: keys are binary32 patterns
     uint32_t* err;
 };
+
+// Sorting tiles of uneven length by pieces and merges (merge.hip).
+constexpr int MERGE_PIECE = 4096;          // keys per wavefront work item
+constexpr int MERGE_POS_BITS = 20;         // tile positions fit in 20 bits
+constexpr int64_t MERGE_MAX_TILE = int64_t(1) << MERGE_POS_BITS;
+constexpr int MERGE_MAX_ROUNDS = 8;        // log2(MERGE_MAX_TILE / MERGE_PIECE)
+constexpr int MERGE_COUNTER_WORD = 16;     // first counter word in the workspace header
+constexpr int MERGE_COUNTER_BYTES = 64;    // words 16 .. 31: 4 bins, pieces, rounds 0 .. 7
+
+// Byte offsets of the regions a merge-schedule sort carves out of the workspace.
+struct MergeLayout {
+    int64_t cap;       // entries per piece list and per round list
+    int rounds;        // merge rounds provisioned (0 when max_len <= MERGE_PIECE)
+    size_t bins, pieces, round_lists, coranks, run0, run1, total;
+};
+MergeLayout merge_layout(int64_t num_tiles, int64_t total_len, int64_t max_len);
+
+struct MergeArgs {
+    SortArgs s;
+    uint32_t* counters;      // MERGE_COUNTER_BYTES, zeroed by the launcher
+    uint64_t* bins;          // 4 lists of num_tiles entries (tile << 16)
+    uint64_t* pieces;        // cap entries (tile << 16 | piece)
+    uint64_t* round_lists;   // rounds x cap entries (tile << 16 | output piece)
+    int32_t* coranks;        // rounds x cap x 2
+    uint64_t* run0;          // total_len composites
+    uint64_t* run1;          // total_len composites (only when rounds >= 2)
+    int64_t cap;
+    int rounds;
+    int pack;                // nonzero: up to 8 short tiles share one wavefront
+    int64_t max_len;
+    int64_t total_len;       // keys of all tiles; every tile must lie in [0, total_len)
+};
+hipError_t launch_sort_merge(const SortArgs& s, int64_t total_len, int64_t max_len, void* ws,
+                             hipStream_t st);
+void set_merge_pack(int v);
 
 // Device properties cached by the API layer.
 int num_cus();

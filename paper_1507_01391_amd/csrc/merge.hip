@@ -1,0 +1,461 @@
+// Sorting a batch of tiles of uneven length (1 .. 2^20 keys each) in a fixed sequence of
+// launches that a stream capture can record once and replay.
+//
+// The tile-local problem is the paper's sorting problem (Sec. 1, "Problems of
+// interest"); its schedules assume a w x m tile resident in one workgroup.  Here a
+// tile longer than one wavefront's 4096 items is cut into pieces, every piece is sorted
+// in registers by the bitonic network of bitonic.hpp (conflict-free transposes through
+// LDS), and sorted runs are merged pairwise, doubling the run length per round.  A
+// merge step is the last level of the same bitonic network, applied to 4096 outputs at
+// a time: a merge-path co-rank search picks the A and B ranges that produce them, A is
+// loaded ascending and B descending (a bitonic sequence) and 12 merge stages sort it.
+//
+// Items are 64-bit composites  slot << 52 | key << 20 | position,  distinct within a
+// tile, so the result is the unique stable order.  `slot` packs up to eight tiles of at
+// most 512 keys (four of 1024, two of 2048) into one wavefront: each tile owns a slot of
+// 4096 / P positions and its padding sorts to the end of its slot.
+//
+// Sequence of launches (all on one stream, no host synchronisation):
+//   1. clear the work counters (a fill kernel, so the sequence stays capturable);
+//   2. bin: one thread per tile appends the tile to a packing bin or its pieces to the
+//      piece list, and its output pieces to the list of every merge round it needs;
+//   3. sort: one persistent launch over all bins and pieces;
+//   4. per merge round: co-rank search (one thread per output piece), then the merge.
+// The last store of every tile writes keys, the permutation and the payload, gathered
+// from the input by the permutation.
+#include "bitonic.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ts {
+
+namespace {
+
+using namespace bt;
+
+constexpr int K = MERGE_PIECE;
+constexpr int POS_BITS = MERGE_POS_BITS;
+constexpr uint64_t POS_MASK = (uint64_t(1) << POS_BITS) - 1;
+constexpr int SLOT_SHIFT = 52;
+constexpr uint64_t PAD = ~uint64_t(0);
+
+int g_merge_pack = 1;
+
+TS_DEV uint64_t make_comp(uint32_t slot, uint32_t key, uint32_t pos) {
+    return ((uint64_t)slot << SLOT_SHIFT) | ((uint64_t)key << POS_BITS) | pos;
+}
+TS_DEV uint32_t comp_key(uint64_t c) { return (uint32_t)(c >> POS_BITS); }
+TS_DEV uint32_t comp_pos(uint64_t c) { return (uint32_t)(c & POS_MASK); }
+
+TS_DEV uint64_t entry(int64_t tile, uint32_t j) { return ((uint64_t)tile << 16) | j; }
+TS_DEV int64_t entry_tile(uint64_t e) { return (int64_t)(e >> 16); }
+TS_DEV uint32_t entry_j(uint64_t e) { return (uint32_t)(e & 0xFFFFu); }
+
+TS_DEV uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+TS_DEV int64_t uniform64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    return (int64_t)(((uint64_t)uniform((uint32_t)(u >> 32)) << 32) | uniform((uint32_t)u));
+}
+
+// Append `cnt` entries (tile, 0 .. cnt-1) per lane to `list`, one atomic per wave.
+// Entries past `cap` are dropped and reported (tiles overlapping in a malformed offset
+// array could otherwise need more entries than the workspace holds).
+TS_DEV void wave_append(uint32_t* counter, uint64_t* list, int64_t cap, uint32_t* err,
+                        uint32_t cnt, int64_t tile, int lane) {
+    uint32_t x = cnt;  // inclusive scan over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d);
+        if (lane >= d) x += y;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)x, 63);
+    if (total == 0) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(counter, total);
+    base = (uint32_t)__shfl((int)base, 0);
+    const uint32_t start = base + x - cnt;
+    const bool over = (int64_t)start + cnt > cap;
+    flag_error(err, over, ERR_BAD_OFFSETS);
+    for (uint32_t j = 0; j < cnt && (int64_t)(start + j) < cap; ++j) list[start + j] = entry(tile, j);
+}
+
+// Bins: 0 .. 3 pack P = 8, 4, 2, 1 tiles per wavefront (tiles of at most 4096 / P keys).
+TS_DEV int pack_of(int bin) { return 8 >> bin; }
+
+__global__ __launch_bounds__(256) void merge_bin_kernel(MergeArgs a) {
+    const int lane = lane_id();
+    const int64_t T = a.s.num_tiles;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); w0 < T; w0 += stride) {
+        const int64_t t = w0 + lane;
+        int64_t n = 0;
+        bool bad = false;
+        if (t < T) {
+            const int64_t o = a.s.offsets[t];
+            n = a.s.offsets[t + 1] - o;
+            bad = o < 0 || n < 0 || o + n > a.total_len;  // would leave the run buffers
+        }
+        const bool too_long = !bad && n > a.max_len;
+        flag_error(a.s.err, too_long, ERR_TILE_TOO_LONG);
+        flag_error(a.s.err, bad, ERR_BAD_OFFSETS);
+        if (too_long || bad) n = 0;
+        int bin = -1;
+        if (n > 0 && n <= K) bin = a.pack ? (n <= 512 ? 0 : n <= 1024 ? 1 : n <= 2048 ? 2 : 3) : 3;
+        for (int b = 0; b < 4; ++b) {
+            const uint64_t m = ballot(bin == b);
+            if (m == 0) continue;
+            const int leader = __builtin_ctzll(m);
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&a.counters[b], (uint32_t)popc64(m));
+            base = (uint32_t)__shfl((int)base, leader);
+            if (bin == b) a.bins[b * T + base + count_below(m)] = entry(t, 0);
+        }
+        const uint32_t np = (n > K) ? (uint32_t)((n + K - 1) / K) : 0u;
+        wave_append(&a.counters[4], a.pieces, a.cap, a.s.err, np, t, lane);
+        for (int r = 0; r < a.rounds; ++r) {
+            const uint32_t nr = (n > ((int64_t)K << r)) ? np : 0u;
+            wave_append(&a.counters[8 + r], a.round_lists + (int64_t)r * a.cap, a.cap, a.s.err, nr, t,
+                        lane);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Final store of one item of a tile: key, permutation and payload gathered by it.
+TS_DEV void store_final(const SortArgs& s, int64_t o, int64_t rank, uint64_t c) {
+    const uint32_t key = comp_key(c);
+    const uint32_t pos = comp_pos(c);
+    if (s.keys_out) s.keys_out[o + rank] = s.f32 ? ordered_to_f32(key) : key;
+    if (s.perm_out) s.perm_out[o + rank] = (int32_t)pos;
+    const PayloadRef& p = s.pay;
+    for (uint32_t ch = 0; ch < p.channels; ++ch)
+        p.out[(o + rank) * p.es + (int64_t)ch * p.cs] = p.in[(o + (int64_t)pos) * p.es + (int64_t)ch * p.cs];
+}
+
+// Tile of bin entry e (or none past the bin's count): offset and length, wave-uniform.
+TS_DEV void bin_tile(const MergeArgs& a, int bin, uint32_t cnt, uint32_t e, int64_t& o, int& n) {
+    o = 0;
+    n = 0;
+    if (e < cnt) {
+        const int64_t t = entry_tile(a.bins[(int64_t)bin * a.s.num_tiles + e]);
+        o = uniform64(a.s.offsets[t]);
+        n = (int)uniform((uint32_t)(a.s.offsets[t + 1] - o));
+    }
+}
+
+// Stage CPS columns (keys of positions 64 j + lane, j < CPS) of one tile into A at
+// word `w0 + 64 j + lane`, 16 columns per batch of loads; positions >= n get the
+// maximal key.
+template <int CPS>
+TS_DEV void stage_keys(uint32_t* A, const SortArgs& s, int64_t o, int n, int w0, int lane) {
+    constexpr int G = CPS < 16 ? CPS : 16;
+#pragma unroll 1
+    for (int g = 0; g < CPS; g += G) {
+        uint32_t kk[G];
+        load_columns<G>(s.keys_in, 1, o, n, g, lane, kk, s.offsets);
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const uint32_t i = (uint32_t)(64 * (g + j) + lane);
+            const uint32_t key = (i < (uint32_t)n) ? (s.f32 ? f32_to_ordered(kk[j]) : kk[j]) : 0xFFFFFFFFu;
+            lds_store(A, (uint32_t)(w0 + (int)i) * 4u, key);
+        }
+    }
+}
+
+// Packed bin: P tiles, tile s at slot s (positions s*C .. s*C + C-1, C = 4096 / P).
+template <int P>
+TS_DEV void load_packed(uint32_t* A, uint64_t (&v)[R], const MergeArgs& a, int bin, uint32_t cnt,
+                        uint32_t item, int lane) {
+    constexpr int CPS = 64 / P;  // columns per slot
+#pragma unroll
+    for (int sl = 0; sl < P; ++sl) {
+        int64_t o;
+        int n;
+        bin_tile(a, bin, cnt, item * P + sl, o, n);
+        stage_keys<CPS>(A, a.s, o, n, sl * CPS * 64, lane);
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        const uint32_t i = (uint32_t)(64 * c + lane);
+        v[c] = make_comp((uint32_t)(c / CPS), lds_load(A, i * 4u), (uint32_t)(64 * (c % CPS) + lane));
+    }
+}
+
+template <int P>
+TS_DEV void store_packed(const uint64_t (&v)[R], const MergeArgs& a, int bin, uint32_t cnt,
+                         uint32_t item, int lane) {
+    constexpr int CPS = 64 / P;
+#pragma unroll
+    for (int sl = 0; sl < P; ++sl) {
+        int64_t o;
+        int n;
+        bin_tile(a, bin, cnt, item * P + sl, o, n);
+        const int ln = (int)opaque((uint32_t)lane);
+#pragma unroll
+        for (int j = 0; j < CPS; ++j) {
+            const int r = 64 * j + ln;  // rank within the tile
+            if (r < n) store_final(a.s, o, r, v[sl * CPS + j]);
+        }
+    }
+}
+
+// Piece j of a long tile: positions j*4096 .. ; sorted runs go to run0.
+TS_DEV void piece_range(const MergeArgs& a, uint64_t e, int64_t& o, int& n, uint32_t& base) {
+    const int64_t t = entry_tile(e);
+    const uint32_t j = entry_j(e);
+    const int64_t to = uniform64(a.s.offsets[t]);
+    const int64_t tn = uniform64(a.s.offsets[t + 1] - to);
+    base = j * (uint32_t)K;
+    o = to + base;
+    const int64_t rem = tn - (int64_t)base;
+    n = (int)(rem < K ? rem : K);
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+void merge_sort_kernel(MergeArgs a) {
+    __shared__ uint32_t A[MOVE_WORDS];
+    uint32_t cnt[5], start[6];
+    start[0] = 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        cnt[b] = uniform(a.counters[b]);
+        if (b == 4 && cnt[b] > (uint32_t)a.cap) cnt[b] = (uint32_t)a.cap;
+        const uint32_t items = (b < 4) ? (cnt[b] + pack_of(b) - 1) / pack_of(b) : cnt[b];
+        start[b + 1] = start[b] + items;
+    }
+    for (uint32_t w = blockIdx.x; w < start[5]; w += gridDim.x) {
+        const int lane = (int)opaque((uint32_t)lane_id());
+        int kind = 4;
+        uint32_t item = w - start[4];
+        if (w < start[1]) { kind = 0; item = w; }
+        else if (w < start[2]) { kind = 1; item = w - start[1]; }
+        else if (w < start[3]) { kind = 2; item = w - start[2]; }
+        else if (w < start[4]) { kind = 3; item = w - start[3]; }
+        uint64_t v[R];
+        switch (kind) {
+            case 0: load_packed<8>(A, v, a, 0, cnt[0], item, lane); break;
+            case 1: load_packed<4>(A, v, a, 1, cnt[1], item, lane); break;
+            case 2: load_packed<2>(A, v, a, 2, cnt[2], item, lane); break;
+            case 3: load_packed<1>(A, v, a, 3, cnt[3], item, lane); break;
+            default: {
+                int64_t o;
+                int n;
+                uint32_t base;
+                piece_range(a, a.pieces[item], o, n, base);
+                stage_keys<64>(A, a.s, o, n, 0, lane);
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const uint32_t i = (uint32_t)(64 * c + lane);
+                    v[c] = make_comp(0u, lds_load(A, i * 4u), base + i);
+                }
+            }
+        }
+        bitonic_sort4096(A, v, lane);
+        switch (kind) {
+            case 0: store_packed<8>(v, a, 0, cnt[0], item, lane); break;
+            case 1: store_packed<4>(v, a, 1, cnt[1], item, lane); break;
+            case 2: store_packed<2>(v, a, 2, cnt[2], item, lane); break;
+            case 3: store_packed<1>(v, a, 3, cnt[3], item, lane); break;
+            default: {
+                int64_t o;
+                int n;
+                uint32_t base;
+                piece_range(a, a.pieces[item], o, n, base);
+                const int ln = (int)opaque((uint32_t)lane);
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const int r = 64 * c + ln;
+                    if (r < n) a.run0[o + r] = v[c];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Merge round r: runs of length L = 4096 << r are merged in pairs.  Output piece u of a
+// tile covers outputs u*4096 .. of the pair p = u >> (r+1) that starts at ps.
+struct PieceGeom {
+    int64_t o, n;      // tile
+    int64_t ps;        // pair start (tile position)
+    int64_t la, lb;    // lengths of the pair's two runs (lb may be 0)
+    int64_t d0, d1;    // output range within the pair
+    bool last;         // this round finishes the tile
+};
+
+TS_DEV PieceGeom piece_geom(const MergeArgs& a, uint64_t e, int r) {
+    PieceGeom g;
+    const int64_t t = entry_tile(e);
+    const int64_t u = entry_j(e);
+    g.o = a.s.offsets[t];
+    g.n = a.s.offsets[t + 1] - g.o;
+    const int64_t L = (int64_t)K << r;
+    g.ps = (u >> (r + 1)) * 2 * L;
+    const int64_t rest = g.n - g.ps;
+    g.la = rest < L ? rest : L;
+    g.lb = rest - g.la < L ? rest - g.la : L;
+    g.d0 = u * K - g.ps;
+    const int64_t d1 = g.d0 + K;
+    g.d1 = d1 < g.la + g.lb ? d1 : g.la + g.lb;
+    g.last = 2 * L >= g.n;
+    return g;
+}
+
+// Number of A elements among the d smallest of the union of A and B (all distinct).
+TS_DEV int64_t corank(const uint64_t* A, int64_t la, const uint64_t* B, int64_t lb, int64_t d) {
+    int64_t lo = d - lb > 0 ? d - lb : 0;
+    int64_t hi = d < la ? d : la;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (A[mid] > B[d - 1 - mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void merge_corank_kernel(MergeArgs a, int r) {
+    const uint32_t cnt = a.counters[8 + r] < (uint32_t)a.cap ? a.counters[8 + r] : (uint32_t)a.cap;
+    const uint64_t* list = a.round_lists + (int64_t)r * a.cap;
+    int32_t* cr = a.coranks + (int64_t)r * a.cap * 2;
+    const uint64_t* in = (r & 1) ? a.run1 : a.run0;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+        const PieceGeom g = piece_geom(a, list[e], r);
+        const uint64_t* A = in + g.o + g.ps;
+        const uint64_t* B = A + ((int64_t)K << r);
+        cr[2 * (int64_t)e] = (int32_t)corank(A, g.la, B, g.lb, g.d0);
+        cr[2 * (int64_t)e + 1] = (int32_t)corank(A, g.la, B, g.lb, g.d1);
+    }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+void merge_round_kernel(MergeArgs a, int r) {
+    __shared__ uint32_t A[MOVE_WORDS];
+    const uint32_t cnt = uniform(a.counters[8 + r] < (uint32_t)a.cap ? a.counters[8 + r] : (uint32_t)a.cap);
+    const uint64_t* list = a.round_lists + (int64_t)r * a.cap;
+    const int32_t* cr = a.coranks + (int64_t)r * a.cap * 2;
+    const uint64_t* in = (r & 1) ? a.run1 : a.run0;
+    uint64_t* out_run = (r & 1) ? a.run0 : a.run1;
+    for (uint32_t w = blockIdx.x; w < cnt; w += gridDim.x) {
+        const int lane = (int)opaque((uint32_t)lane_id());
+        const PieceGeom g = piece_geom(a, list[w], r);
+        const int64_t i0 = uniform((uint32_t)cr[2 * (int64_t)w]);
+        const int64_t i1 = uniform((uint32_t)cr[2 * (int64_t)w + 1]);
+        const int la = (int)(i1 - i0);                        // from run A
+        const int lb = (int)((g.d1 - g.d0) - la);             // from run B
+        const int64_t k0 = g.d0 - i0;
+        // element q of the bitonic sequence: A ascending, padding, B descending; all
+        // addresses are 32-bit offsets from the pair's first composite
+        const uint64_t* base = in + uniform64(g.o + g.ps);
+        const uint32_t offA = (uint32_t)i0;
+        const uint32_t offB = (uint32_t)(((int64_t)K << r) + k0 + (K - 1));
+        uint64_t v[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int q = 64 * c + lane;
+            const bool inA = q < la;
+            const bool inB = q >= K - lb;
+            const uint32_t idx = inA ? offA + (uint32_t)q : (inB ? offB - (uint32_t)q : 0u);
+            const uint64_t x = *(const uint64_t*)((const char*)base + idx * 8u);
+            v[c] = (inA || inB) ? x : PAD;
+            if ((c & 15) == 15) __builtin_amdgcn_sched_barrier(0);  // bound live addresses
+        }
+        bitonic_merge4096(A, v, lane);
+        const int ln = (int)opaque((uint32_t)lane);
+        const int64_t ob = g.ps + g.d0;  // tile position of output rank 0
+        const int nout = (int)(g.d1 - g.d0);
+        if (g.last) {
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                const int q = 64 * c + ln;
+                if (q < nout) store_final(a.s, g.o, ob + q, v[c]);
+            }
+        } else {
+            uint64_t* ob_ptr = out_run + g.o + ob;
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                const int q = 64 * c + ln;
+                if (q < nout) ob_ptr[q] = v[c];
+            }
+        }
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int rounds_for(int64_t max_len) {
+    int r = 0;
+    while (((int64_t)K << r) < max_len) ++r;
+    return r;
+}
+
+}  // namespace
+
+void set_merge_pack(int v) { g_merge_pack = v; }
+
+MergeLayout merge_layout(int64_t num_tiles, int64_t total_len, int64_t max_len) {
+    MergeLayout L{};
+    L.rounds = rounds_for(max_len);
+    L.cap = total_len / K + num_tiles + 1;
+    size_t off = 256;  // header: error word and counters
+    L.bins = off;
+    off += align256((size_t)num_tiles * 4 * 8);
+    L.pieces = off;
+    off += align256((size_t)L.cap * 8);
+    L.round_lists = off;
+    off += align256((size_t)L.rounds * L.cap * 8);
+    L.coranks = off;
+    off += align256((size_t)L.rounds * L.cap * 8);
+    L.run0 = off;
+    off += align256(L.rounds >= 1 ? (size_t)total_len * 8 : 0);
+    L.run1 = off;
+    off += align256(L.rounds >= 2 ? (size_t)total_len * 8 : 0);
+    L.total = off;
+    return L;
+}
+
+hipError_t launch_sort_merge(const SortArgs& s, int64_t total_len, int64_t max_len, void* ws,
+                             hipStream_t st) {
+    if (s.num_tiles == 0) return hipSuccess;
+    const MergeLayout L = merge_layout(s.num_tiles, total_len, max_len);
+    char* w = (char*)ws;
+    MergeArgs a{};
+    a.s = s;
+    a.counters = (uint32_t*)ws + MERGE_COUNTER_WORD;
+    a.bins = (uint64_t*)(w + L.bins);
+    a.pieces = (uint64_t*)(w + L.pieces);
+    a.round_lists = (uint64_t*)(w + L.round_lists);
+    a.coranks = (int32_t*)(w + L.coranks);
+    a.run0 = (uint64_t*)(w + L.run0);
+    a.run1 = (uint64_t*)(w + L.run1);
+    a.cap = L.cap;
+    a.rounds = L.rounds;
+    a.pack = g_merge_pack;
+    a.max_len = max_len;
+    a.total_len = total_len;
+
+    hipError_t e = launch_fill_zero(a.counters, MERGE_COUNTER_BYTES, st);
+    if (e != hipSuccess) return e;
+    {
+        int64_t g = (s.num_tiles + 255) / 256;
+        if (g > 4096) g = 4096;
+        hipLaunchKernelGGL(merge_bin_kernel, dim3((unsigned)g), dim3(256), 0, st, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+        const int g = persistent_grid((const void*)merge_sort_kernel, 64, 0, s.num_tiles + L.cap);
+        hipLaunchKernelGGL(merge_sort_kernel, dim3(g), dim3(64), 0, st, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    for (int r = 0; r < L.rounds; ++r) {
+        int64_t gc = (L.cap + 255) / 256;
+        if (gc > 2048) gc = 2048;
+        hipLaunchKernelGGL(merge_corank_kernel, dim3((unsigned)gc), dim3(256), 0, st, a, r);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int g = persistent_grid((const void*)merge_round_kernel, 64, 0, L.cap);
+        hipLaunchKernelGGL(merge_round_kernel, dim3(g), dim3(64), 0, st, a, r);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace ts

@@ -160,6 +160,7 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
                     zb += (q < w) ? v : 0;
                 }
             }
+            if (NW == 1) wave_lds_fence();  // the previous pass's reads stay before these writes
             // Write: zeros of column k go to z + rank0, ones to N-1-(ones before)-rank1.
             int z = zb;  // zeros before the current column (whole tile, in order)
 #pragma unroll
@@ -176,6 +177,7 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
             }
             if (NW == 1) zt = z;
             if (NW > 1) __syncthreads();  // the split tile is complete
+            else wave_lds_fence();
             // Read back in virtual order: zero block forward, then one block backward.
             const uint32_t rev_base =
                 (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 + zt - 64 * w * CPW - 64 * (CPW - 1)) * 8) +

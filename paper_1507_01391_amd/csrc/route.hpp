@@ -63,6 +63,7 @@ struct Router {
                     zb += (q >= first && q < w) ? v : 0;
                 }
             }
+            if (!shared) wave_lds_fence();  // the previous level's reads stay before these writes
             int z = zb;
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
@@ -83,6 +84,7 @@ struct Router {
                 z += 64 - popc64(bal);
             }
             if (shared) __syncthreads();  // the level is complete in every segment
+            else wave_lds_fence();
 #pragma unroll
             for (int j = 0; j < CPW; ++j) e[j] = lds_load(A, own_base + 512u * j);
         }

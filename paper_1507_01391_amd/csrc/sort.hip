@@ -11,10 +11,9 @@
 //  * direction masks: a row (or super-row) sorted descending is sorted ascending
 //    on complemented composites, which reverses their order;
 //  * layout moves through LDS: each lane writes register c to the slot of its
-//    destination (lane L', register c') and then reads its new registers.  The
-//    slot of (L', c') is c' * 64 + ((L' + h(c')) mod 64) with a per-move skew h
-//    chosen so that every read instruction (32-lane phases of 8-byte slots) and
-//    every write instruction (16-lane phases) touches distinct banks.
+//    destination (lane L', register c') and then reads its new registers, one 32-bit
+//    plane of the composites at a time, with slots skewed so that every 32-lane
+//    phase of every read and write instruction touches distinct banks.
 //
 // THM2 follows Sec. 2, Theorem 2 for w = m = 64 with super-rows of 8 rows:
 // Lemma 1 on every super-row (two rounds of {rows in alternating order,
@@ -26,6 +25,7 @@
 // BITONIC is Batcher's bitonic network on the 4096 items, with the stages on
 // register bits done in registers and the stages on lane bits done in registers
 // after a conflict-free transpose (the same transpose the column sort uses).
+#include "bitonic.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -33,104 +33,7 @@ namespace ts {
 
 namespace {
 
-constexpr int R = 64;  // registers (columns) per lane
-
-TS_DEV void cas(uint64_t& a, uint64_t& b) {  // afterwards a <= b
-    const bool s = b < a;
-    const uint64_t lo = s ? b : a;
-    const uint64_t hi = s ? a : b;
-    a = lo;
-    b = hi;
-}
-
-// Ascending bitonic sort of the 64 registers of every lane (672 compare-exchanges).
-TS_DEV void row_sort(uint64_t (&v)[R]) {
-#pragma unroll
-    for (int k = 2; k <= R; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    if ((i & k) == 0) cas(v[i], v[l]);
-                    else cas(v[l], v[i]);
-                }
-            }
-        }
-    }
-}
-
-// Ascending bitonic merge of the 64 registers of every lane (stages 32 .. 1).
-TS_DEV void row_merge(uint64_t (&v)[R]) {
-#pragma unroll
-    for (int j = R >> 1; j > 0; j >>= 1) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const int l = i ^ j;
-            if (l > i) cas(v[i], v[l]);
-        }
-    }
-}
-
-// Stages j = 2^(KB-1) .. 1 of bitonic level 2^KB on the register index, direction
-// given by bit KB of the register index (ascending when clear).
-template <int KB>
-TS_DEV void reg_level_stages(uint64_t (&v)[R]) {
-#pragma unroll
-    for (int j = 1 << (KB - 1); j > 0; j >>= 1) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const int l = i ^ j;
-            if (l > i) {
-                if (((i >> KB) & 1) == 0) cas(v[i], v[l]);
-                else cas(v[l], v[i]);
-            }
-        }
-    }
-}
-
-TS_DEV void xor_all(uint64_t (&v)[R], uint64_t m) {
-#pragma unroll
-    for (int i = 0; i < R; ++i) v[i] ^= m;
-}
-
-enum Move : int { MOVE_NONE = 0, MOVE_T = 1, MOVE_RM2CM = 2, MOVE_CM2RM = 3 };
-
-// Destination (lane, register) of register c of lane L, and the slot skew h(c').
-TS_DEV void move_dst(int move, int L, int c, int& Ld, int& cd) {
-    if (move == MOVE_T) {
-        Ld = c;
-        cd = L;
-    } else if (move == MOVE_RM2CM) {  // super-row of 8 rows: row-major p = 64 i + c
-        Ld = (L & ~7) + (c & 7);
-        cd = 8 * (L & 7) + (c >> 3);
-    } else {  // MOVE_CM2RM: column-major p = 8 c + i
-        Ld = (L & ~7) + (c >> 3);
-        cd = 8 * (c & 7) + (L & 7);
-    }
-}
-TS_DEV int move_skew(int move, int cd) {
-    return move == MOVE_T ? cd : (move == MOVE_RM2CM ? (cd >> 3) : (cd & 7));
-}
-
-// Apply a layout move through the LDS array A (4096 slots of 8 bytes).  One wave.
-TS_DEV void layout_move(uint64_t* A, uint64_t (&v)[R], int move, int lane_in) {
-    const int lane = (int)opaque((uint32_t)lane_in);  // keep addresses out of outer loops
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-        int Ld, cd;
-        move_dst(move, lane, c, Ld, cd);
-        const uint32_t slot = (uint32_t)(cd * 64 + ((Ld + move_skew(move, cd)) & 63));
-        lds_store(A, slot * 8u, v[c]);
-    }
-    // (LDS operations of one wave complete in order: the reads see the writes)
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-        const uint32_t slot = (uint32_t)(c * 64 + ((lane + move_skew(move, c)) & 63));
-        v[c] = lds_load(A, slot * 8u);
-    }
-}
+using namespace bt;
 
 // One phase of a schedule: xor with `pre`, row sort, xor with `post`, then a layout
 // move.
@@ -168,11 +71,13 @@ __constant__ Phase kThm2[13] = {
 };
 
 template <int SCHED>  // 2 = THM2, 3 = BITONIC
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
-    __shared__ uint64_t A[4096];
-    const int lane = lane_id();
+    __shared__ uint32_t A[MOVE_WORDS];
     for (int64_t t = blockIdx.x; t < a.num_tiles; t += gridDim.x) {
+        // lane-derived values are recomputed per tile rather than kept live (and
+        // spilled) across the whole loop
+        const int lane = (int)opaque((uint32_t)lane_id());
         const int64_t o = offs[t];
         const int64_t len = offs[t + 1] - o;
         if (len > 4096) {
@@ -180,17 +85,23 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
             continue;
         }
         const int n = (int)len;
-        // ---- load: register c, lane L = item 64c + L (coalesced); padding sorts last
-        uint64_t v[R];
-        {
-            uint32_t kk[R];
-            load_columns<R>(a.keys_in, 1, o, n, 0, lane, kk, offs);
+        // ---- load: 16 coalesced columns at a time, staged through LDS (word 64 c + L);
+        // register c of lane L then holds item 64 c + L; padding sorts last
+#pragma unroll 1
+        for (int g = 0; g < R; g += 16) {
+            uint32_t kk[16];
+            load_columns<16>(a.keys_in, 1, o, n, g, lane, kk, offs);
 #pragma unroll
-            for (int c = 0; c < R; ++c) {
-                const uint32_t i = (uint32_t)(64 * c + lane);
-                const uint32_t key = (i < (uint32_t)n) ? (a.f32 ? f32_to_ordered(kk[c]) : kk[c]) : 0xFFFFFFFFu;
-                v[c] = pack(key, i);
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t i = (uint32_t)(64 * (g + j) + lane);
+                lds_store(A, i * 4u, (i < (uint32_t)n) ? (a.f32 ? f32_to_ordered(kk[j]) : kk[j]) : 0xFFFFFFFFu);
             }
+        }
+        uint64_t v[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const uint32_t i = (uint32_t)(64 * c + lane);
+            v[c] = pack(lds_load(A, i * 4u), i);
         }
 
         if (SCHED == 2) {
@@ -203,34 +114,15 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
                 layout_move(A, v, ph.move, lane);
             }
         } else {
-            // levels 2 .. 64: rows sorted, odd rows descending
-            xor_all(v, mask_of(1, lane));
-            row_sort(v);
-            xor_all(v, mask_of(1, lane));
-#pragma unroll 1
-            for (int kb = 1; kb <= 6; ++kb) {
-                layout_move(A, v, MOVE_T, lane);  // lane bits become register bits
-                switch (kb) {
-                    case 1: reg_level_stages<1>(v); break;
-                    case 2: reg_level_stages<2>(v); break;
-                    case 3: reg_level_stages<3>(v); break;
-                    case 4: reg_level_stages<4>(v); break;
-                    case 5: reg_level_stages<5>(v); break;
-                    default: reg_level_stages<6>(v); break;
-                }
-                layout_move(A, v, MOVE_T, lane);  // back: register bits
-                const uint64_t m = (kb < 6) ? mask_of(8 + kb, lane) : 0ull;
-                xor_all(v, m);
-                row_merge(v);
-                xor_all(v, m);
-            }
-            layout_move(A, v, MOVE_T, lane);  // to store order
+            bitonic_sort4096(A, v, lane);
         }
 
-        // ---- store: register c, lane L holds rank 64 c + L
+        // ---- store: register c, lane L holds rank 64 c + L (addresses computed here,
+        // not hoisted above the network)
+        const int sl = (int)opaque((uint32_t)lane);
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            const int r = 64 * c + lane;
+            const int r = 64 * c + sl;
             if (r < n) {
                 const uint32_t key = hi32(v[c]);
                 if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);

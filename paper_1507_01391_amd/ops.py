@@ -27,17 +27,21 @@ def _stream(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def workspace(device=None) -> torch.Tensor:
-    """Per-device workspace (error word + counters), zeroed once on creation."""
+def workspace(device=None, nbytes: int = 0) -> torch.Tensor:
+    """Per-device workspace (error word, counters and schedule scratch), zeroed on
+    creation.  Grows to at least `nbytes`; the error word is carried over."""
     dev = torch.device("cuda", torch.cuda.current_device() if device is None else
                        torch.device(device).index or 0)
     ws = _workspaces.get(dev)
-    if ws is None:
-        lib = _lib.load()
-        nbytes = lib.ts_workspace_bytes(0, 0, 0, 0)
-        ws = torch.empty(nbytes // 4, dtype=torch.int32, device=dev)
-        _lib.check(lib.ts_workspace_init(_ptr(ws), nbytes, _stream(dev)))
-        _workspaces[dev] = ws
+    lib = _lib.load()
+    need = max(int(nbytes), lib.ts_workspace_bytes(0, 0, 0, 0, 0, 0))
+    if ws is None or ws.numel() * 4 < need:
+        size = (need + 255) // 256 * 256
+        new = torch.empty(size // 4, dtype=torch.int32, device=dev)
+        _lib.check(lib.ts_workspace_init(_ptr(new), size, _stream(dev)))
+        if ws is not None:
+            new[:64].copy_(ws[:64])   # 256-byte header: pending error bits
+        _workspaces[dev] = ws = new
     return ws
 
 
@@ -167,13 +171,14 @@ def tile_sort(keys: torch.Tensor, payload: Optional[torch.Tensor] = None, offset
         keys_out = torch.empty_like(keys)
     if want_perm and perm_out is None:
         perm_out = torch.empty(n, dtype=torch.int32, device=dev)
-    ws = workspace(dev)
     flags = _lib.sched_flags(schedule) | (_lib.TS_FLAG_F32_ORDERED if f32_ordered else 0)
     lib = _lib.load()
+    T = off.numel() - 1
+    ml = _max_len(off, max_tile_len)
+    ws = workspace(dev, lib.ts_workspace_bytes(_lib.TS_OP_SORT, flags, T, n, ml, ch))
     _lib.check(lib.tile_sort(_ptr(keys), _ptr(keys_out), _ptr(payload), _ptr(payload_out), ch, es,
-                             cs, _ptr(perm_out), _ptr(off), off.numel() - 1,
-                             _max_len(off, max_tile_len), flags, _ptr(ws), ws.numel() * 4,
-                             _stream(dev)))
+                             cs, _ptr(perm_out), _ptr(off), T, n, ml, flags, _ptr(ws),
+                             ws.numel() * 4, _stream(dev)))
     return keys_out, payload_out, perm_out
 
 
@@ -200,6 +205,15 @@ def lds_probe(lane_words: Sequence[int], op: str = "read", width: int = 1, iters
     return cycles, sink
 
 
+_knobs: dict = {}
+
+
 def tune(knob: str, value: int) -> None:
     """Override one entry of the library's kernel-selection table (see ts_tune)."""
     _lib.check(_lib.load().ts_tune(knob.encode(), int(value)))
+    _knobs[knob] = int(value)
+
+
+def knob(name: str, default: Optional[int] = None) -> Optional[int]:
+    """The last value set for a knob through tune() in this process (else `default`)."""
+    return _knobs.get(name, default)

@@ -37,7 +37,15 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_version_and_workspace_size(lib):
     assert b"gfx950" in lib.ts_version()
-    assert lib.ts_workspace_bytes(1, 10, 4096, 1) >= 4
+    assert lib.ts_workspace_bytes(1, 0, 10, 40960, 4096, 1) >= 256
+    # the merge schedule keeps two runs of 8-byte composites plus work lists
+    merge = 4 << 8
+    n, tiles = 1 << 20, 64
+    assert lib.ts_workspace_bytes(0, merge, tiles, n, 32768, 1) >= 16 * n
+    # AUTO takes the merge schedule beyond 16384 keys per tile
+    assert lib.ts_workspace_bytes(0, 0, tiles, n, 32768, 0) == lib.ts_workspace_bytes(0, merge, tiles, n, 32768, 0)
+    # a single piece per tile needs no runs
+    assert lib.ts_workspace_bytes(0, merge, tiles, n, 4096, 0) < 2 * n
 
 
 def _err(lib):
@@ -63,3 +71,39 @@ def test_partition_argument_validation(lib):
     # tile too long for any kernel
     rc = lib.tile_partition(fake, P(0x3000), None, None, 0, 1, 0, 64, None, fake, 1, 1 << 20, 0, ws, 256, None)
     assert rc == 2
+
+
+def test_sort_argument_validation(lib):
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    ws = P(0x2000)
+    merge = 4 << 8
+    # total_len < 0
+    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, -1, 4096, 0, ws, 256, None)
+    assert rc == 1 and "total_len" in _err(lib)
+    # aliasing
+    rc = lib.tile_sort(fake, fake, None, None, 0, 1, 0, None, fake, 1, 4096, 4096, 0, ws, 256, None)
+    assert rc == 1 and "alias" in _err(lib)
+    # the bitonic schedule holds 4096 keys per tile
+    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 8192, 8192, 3 << 8, ws, 256, None)
+    assert rc == 2
+    # the merge schedule holds 2^20 keys per tile
+    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 1 << 21, (1 << 20) + 1, merge,
+                       ws, 1 << 30, None)
+    assert rc == 2
+    # the merge schedule needs its workspace
+    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 65536, 65536, merge, ws, 256, None)
+    assert rc == 4 and "workspace" in _err(lib)
+    # no tiles: nothing to do, nothing launched
+    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 0, 0, 0, merge, ws, 256, None)
+    assert rc == 0
+
+
+def test_tune_knob_validation(lib):
+    assert lib.ts_tune(b"sort_plan_8192", 3) == 1          # bitonic cannot hold 8192 keys
+    assert lib.ts_tune(b"sort_plan_4096", 7) == 1
+    assert lib.ts_tune(b"merge_pack", 2) == 1
+    assert lib.ts_tune(b"no_such_knob", 0) == 1
+    assert lib.ts_tune(b"sort_plan_16384", 4) == 0
+    assert lib.ts_tune(b"sort_plan_16384", 1) == 0         # back to the default
+    assert lib.ts_tune(b"merge_pack", 1) == 0

@@ -62,11 +62,12 @@ def test_large_tiles(ts, oracle, schedule, cap):
 @pytest.mark.parametrize("waves", [1, 2, 4, 8, 16, 104, 106, 108, 118, 204, 208, 216])
 def test_wave_count_variants(ts, oracle, waves):
     labels, payload, off = inputs.partition(seed=30 + waves, num_tiles=40, n=4096)
+    prev = ts.knob("partition_waves_4096", 106)
     ts.tune("partition_waves_4096", waves)
     try:
         run_and_compare(ts, oracle, labels, payload, off, 64, "split", max_len=4096)
     finally:
-        ts.tune("partition_waves_4096", 106)
+        ts.tune("partition_waves_4096", prev)
 
 
 def test_no_payload_and_degenerate_labels(ts, oracle):

@@ -78,10 +78,11 @@ def test_validate_reports_non_permutation(ts, direction):
 @pytest.mark.parametrize("direction", ["scatter", "gather"])
 def test_permute_variants(ts, oracle, variant, direction):
     x, pi, _, off = inputs.permutation(seed=43, num_tiles=24, n=8192, family="uniform")
+    prev = ts.knob("permute_variant", 0)
     ts.tune("permute_variant", variant)
     try:
         run_and_compare(ts, oracle, x, pi, off, direction, max_len=8192)
         x4, pi4, _, off4 = inputs.permutation(seed=44, num_tiles=24, n=4096, family="uniform")
         run_and_compare(ts, oracle, x4, pi4, off4, direction, max_len=4096)
     finally:
-        ts.tune("permute_variant", 0)
+        ts.tune("permute_variant", prev)

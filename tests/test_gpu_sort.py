@@ -6,7 +6,7 @@ from paper_1507_01391_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-SMALL_SCHEDULES = ["bitonic", "thm2", "split", "naive"]
+SMALL_SCHEDULES = ["bitonic", "thm2", "split", "naive", "merge"]
 
 
 @pytest.fixture(scope="module")
@@ -78,7 +78,7 @@ def test_f32_keys_with_special_values(ts, oracle, schedule):
     run_and_compare(ts, oracle, x.view(np.uint32), payload.view(np.uint32), off, schedule, f32=True)
 
 
-@pytest.mark.parametrize("schedule", ["split", "naive", "auto"])
+@pytest.mark.parametrize("schedule", ["split", "naive", "auto", "merge"])
 @pytest.mark.parametrize("cap", [8192, 16384])
 def test_large_tiles(ts, oracle, schedule, cap):
     rng = np.random.default_rng(cap)
@@ -93,3 +93,100 @@ def test_large_tiles(ts, oracle, schedule, cap):
 def test_segments_workload_sample(ts, oracle):
     keys, payload, off, _ = inputs.segments(seed=11, num_segments=60, hi=16384)
     run_and_compare(ts, oracle, keys, payload, off, "auto", max_len=16384)
+
+
+# ---- merge schedule: tiles longer than one workgroup, packing of short tiles --------
+
+EDGE_SIZES = [0, 1, 2, 63, 64, 65, 511, 512, 513, 1024, 1025, 2048, 2049, 4095, 4096, 4097,
+              8191, 8192, 8193, 12289, 16384, 16385, 20000, 32767, 32768]
+
+
+@pytest.mark.parametrize("pack", [1, 0])
+def test_merge_edge_sizes(ts, oracle, pack):
+    rng = np.random.default_rng(21 + pack)
+    sizes = np.array(EDGE_SIZES)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    keys = rng.integers(0, 50, size=off[-1], dtype=np.uint32)           # heavy ties
+    keys[::5] = rng.integers(0, 2**32, size=keys[::5].shape[0], dtype=np.uint32)
+    payload = np.stack([np.arange(off[-1], dtype=np.uint32),
+                        rng.integers(0, 2**32, size=off[-1], dtype=np.uint32)])
+    prev = ts.knob("merge_pack", 1)
+    ts.tune("merge_pack", pack)
+    try:
+        run_and_compare(ts, oracle, keys, payload, off, "merge", max_len=32768)
+    finally:
+        ts.tune("merge_pack", prev)
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_merge_segments_workload_sample(ts, oracle, seed):
+    keys, payload, off, kinds = inputs.segments(seed=seed, num_segments=300, hi=32768)
+    assert set(kinds.tolist()) == set(range(len(inputs.SEGMENT_KINDS)))
+    run_and_compare(ts, oracle, keys, payload, off, "auto", max_len=32768)
+
+
+def test_merge_f32_keys_long_tiles(ts, oracle):
+    rng = np.random.default_rng(31)
+    sizes = [30000, 9000, 4096, 700, 32768]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = rng.standard_normal(off[-1]).astype(np.float32)
+    x[:10] = np.array([-np.inf, np.inf, -0.0, 0.0, 1e-40, -1e-40, 3.0, -3.0, 0.0, -0.0], np.float32)
+    x[40000:40010] = x[:10]
+    pay = rng.uniform(-1, 1, size=off[-1]).astype(np.float32)
+    run_and_compare(ts, oracle, x.view(np.uint32), pay.view(np.uint32), off, "merge",
+                    max_len=32768, f32=True)
+
+
+def test_merge_long_tile_up_to_limit(ts, oracle):
+    rng = np.random.default_rng(41)
+    sizes = [1 << 20, 100000, 3]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    keys = rng.integers(0, 2**32, size=off[-1], dtype=np.uint32)
+    keys[:300000] = rng.integers(0, 1000, size=300000, dtype=np.uint32)
+    run_and_compare(ts, oracle, keys, None, off, "merge", max_len=1 << 20)
+
+
+def test_merge_skips_tiles_outside_the_arrays(ts):
+    from tests.gpu_util import dev
+    keys = np.arange(4000, dtype=np.uint32)[::-1].copy()
+    off = np.array([0, 100, 5000], np.int64)             # tile 1 ends past the 4000 keys
+    ts.tile_sort(dev(keys), None, dev(off), max_tile_len=8192, schedule="merge")
+    with pytest.raises(RuntimeError, match="total_len"):
+        ts.check_device_errors()
+
+
+def test_merge_graph_replay(ts, oracle):
+    """The launch sequence captured once (stream capture) and replayed: every replay,
+    with eager work on the same buffers in between, equals the eager result."""
+    import torch
+    from tests.gpu_util import dev
+    keys, payload, off, _ = inputs.segments(seed=13, num_segments=120, hi=32768)
+    wk, wp, wperm = oracle.tile_sort(keys, payload, off, nthreads=8)
+    d_k, d_p, d_o = dev(keys), dev(payload), dev(off)
+    ko, po, pm = torch.empty_like(d_k), torch.empty_like(d_p), torch.empty(len(keys), dtype=torch.int32, device="cuda")
+
+    def call():
+        ts.tile_sort(d_k, d_p, d_o, max_tile_len=32768, schedule="merge", keys_out=ko,
+                     payload_out=po, perm_out=pm)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        call()                                   # warm-up: workspace and launch caches
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    for rep in range(3):
+        ko.fill_(0)
+        pm.fill_(-1)
+        po.fill_(7)
+        ts.tile_sort(d_k, None, d_o, max_tile_len=32768, schedule="merge")   # eager work between
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(ko.cpu().numpy().view(np.uint32), wk.view(np.uint32)), rep
+        assert np.array_equal(pm.cpu().numpy(), wperm), rep
+        assert np.array_equal(po.cpu().numpy().view(np.uint32), np.asarray(wp).view(np.uint32)), rep
+    ts.check_device_errors()
