@@ -68,7 +68,7 @@ def cpu_baseline_partition(labels, payload, offsets, oracle, min_seconds=10.0):
         oracle.tile_partition(lab, pay, off, num_classes=64, nthreads=cores)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= min_seconds or reps >= 50:
+        if el >= min_seconds or reps >= 2000:
             break
     return n * reps / el, cores, f"{tiles} of {len(offsets) - 1} tiles ({n} keys), {reps} repetitions, {el:.1f} s"
 
@@ -138,8 +138,12 @@ def bench_c2(args, torch, ts, inputs):
         w4, m4, _ = timed_launches(lambda: ts.copy(buf, buf2), 10, 3, torch)
         extra["hbm_copy_GBps"] = 2 * (1 << 30) / (m4 / 1e3) / 1e9
         del buf, buf2
-        # C3 fwd + bwd permutation rate (secondary metric)
-        extra.update(bench_c3(args, torch, ts, inputs, quick=True))
+        # secondary workloads: single-tile latency, fwd+bwd permutation, uneven
+        # segmented sort (graph replay), differentiable sort with an 8-channel payload
+        extra.update(bench_c1(torch, ts, inputs))
+        extra.update(bench_c3(args, torch, ts, inputs))
+        extra.update(bench_c4(args, torch, ts, inputs, orc))
+        extra.update(bench_c5(args, torch, ts, inputs))
 
     cpu = None
     if not args.no_cpu:
@@ -174,8 +178,25 @@ def bench_c2(args, torch, ts, inputs):
     }
 
 
-def bench_c3(args, torch, ts, inputs, quick=False):
-    T = 4096 if quick else args.tiles3
+def bench_c1(torch, ts, inputs):
+    """One 4096-key tile with its index payload: latency of one call (all launches)."""
+    keys, payload, off = inputs.single_tile()
+    dk = torch.from_numpy(keys.view(np.int32)).cuda()
+    dp = torch.from_numpy(payload.view(np.int32)).cuda()
+    do = torch.from_numpy(off).cuda()
+    ko, po, pm = torch.empty_like(dk), torch.empty_like(dp), torch.empty_like(dk)
+    out = {}
+    for sched in ("bitonic", "merge", "naive"):
+        _, m, _ = timed_launches(lambda: ts.tile_sort(dk, dp, do, max_tile_len=4096, schedule=sched,
+                                                      keys_out=ko, payload_out=po, perm_out=pm),
+                                 200, 20, torch)
+        out[f"c1_single_tile_us_{sched}"] = m * 1e3
+    return out
+
+
+def bench_c3(args, torch, ts, inputs):
+    """fwd (scatter) + bwd (gather) permutation of 16384 tiles x 8192 fp32."""
+    T = args.tiles3
     x, pi, g, off = inputs.permutation(num_tiles=T, n=8192)
     dx = torch.from_numpy(x).cuda()
     dpi = torch.from_numpy(pi).cuda()
@@ -183,15 +204,71 @@ def bench_c3(args, torch, ts, inputs, quick=False):
     doff = torch.from_numpy(off).cuda()
     y = torch.empty_like(dx)
     gx = torch.empty_like(dx)
+    out = {}
+    for sched in ("split", "naive"):
+        def fwd_bwd():
+            ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y, schedule=sched)
+            ts.tile_permute(dg, dpi, "gather", doff, max_tile_len=8192, out=gx, schedule=sched)
+        log(f"[bench] C3 fwd+bwd permute ({sched}) ...")
+        w, m, _ = timed_launches(fwd_bwd, 10, 3, torch)
+        out[f"c3_permute_fwd_bwd_GBps_{sched}"] = 2 * PERMUTE_BYTES_PER_ELEM * T * 8192 / (m / 1e3) / 1e9
+    out["c3_tiles"] = T
+    del dx, dpi, dg, y, gx
+    return out
 
-    def fwd_bwd():
-        ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y)
-        ts.tile_permute(dg, dpi, "gather", doff, max_tile_len=8192, out=gx)
 
-    w, m, _ = timed_launches(fwd_bwd, 10, 3, torch)
-    n = T * 8192
-    return {"c3_permute_fwd_bwd_GBps": 2 * PERMUTE_BYTES_PER_ELEM * n / (w / 10 / 1e3) / 1e9,
-            "c3_permute_tiles": T}
+def bench_c4(args, torch, ts, inputs, orc):
+    """Uneven segmented sort: 100000 segments of 256..32768 keys (log-uniform), mixed
+    key distributions, uint32 index payload; the launch sequence is captured once
+    and replayed."""
+    S = args.segments
+    log(f"[bench] generating C4 inputs: {S} segments ...")
+    keys, payload, off, _ = inputs.segments(num_segments=S)
+    n = int(off[-1])
+    dk = torch.from_numpy(keys.view(np.int32)).cuda()
+    dp = torch.from_numpy(payload.view(np.int32)).cuda()
+    do = torch.from_numpy(off).cuda()
+    g = ts.sort_graph(dk, do, 32768, payload=dp)
+    log("[bench] C4 graph replay ...")
+    w, m, _ = timed_launches(g.replay, 10, 2, torch)
+    ts.check_device_errors()
+    ko, po, pm = g.result
+    rng = np.random.default_rng(1)
+    ok = True
+    kh, ph = ko.cpu().numpy().view(np.uint32), po.cpu().numpy().view(np.uint32)
+    for s in np.sort(rng.choice(S, size=min(16, S), replace=False)):
+        a, b = int(off[s]), int(off[s + 1])
+        wk, wp, _ = orc.tile_sort(keys[a:b], payload[a:b])
+        ok &= bool(np.array_equal(kh[a:b], wk) and np.array_equal(ph[a:b], wp))
+    out = {"c4_segmented_sort_keys_per_s": n / (m / 1e3),
+           "c4_GBps_16B_per_key": 16 * n / (m / 1e3) / 1e9,
+           "c4_ms_per_replay": m, "c4_keys": n, "c4_segments": S,
+           "c4_parity_sampled_segments": "16 segments bit-exact" if ok else "MISMATCH"}
+    del g, dk, dp, do, ko, po, pm
+    return out
+
+
+def bench_c5(args, torch, ts, inputs):
+    """Differentiable sort-with-payload: rows x 16384 fp32 keys, 8-channel planar fp32
+    payload; forward (sort + gather) and backward (scatter of both gradients)."""
+    R = args.rows5
+    keys, payload, grad, off = inputs.sort_payload(rows=R)
+    dk = torch.from_numpy(keys).cuda().requires_grad_(True)
+    dp = torch.from_numpy(payload).cuda().requires_grad_(True)
+    dg = torch.from_numpy(grad).cuda()
+    gk = torch.from_numpy(np.random.default_rng(5).standard_normal(keys.shape[0], dtype=np.float32)).cuda()
+    do = torch.from_numpy(off).cuda()
+
+    def step():
+        sk, sp, _ = ts.sort_with_payload(dk, dp, do, 16384)
+        torch.autograd.backward([sk, sp], [gk, dg])
+        dk.grad = None
+        dp.grad = None
+    log("[bench] C5 sort-with-payload fwd+bwd ...")
+    w, m, _ = timed_launches(step, 5, 2, torch)
+    n = R * 16384
+    return {"c5_fwd_bwd_keys_per_s": n / (m / 1e3), "c5_fwd_bwd_GBps_144B_per_key": 144 * n / (m / 1e3) / 1e9,
+            "c5_ms_per_step": m, "c5_rows": R}
 
 
 def main():
@@ -201,6 +278,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tiles", type=int, default=65536)
     ap.add_argument("--tiles3", type=int, default=16384)
+    ap.add_argument("--segments", type=int, default=100000)
+    ap.add_argument("--rows5", type=int, default=4096)
     ap.add_argument("--config", default="c2", choices=["c2"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")

@@ -16,7 +16,7 @@ import argparse
 import json
 import os
 import time
-from typing import Callable, Dict, List, Optional
+from typing import Callable, Dict, Optional
 
 import numpy as np
 import torch
@@ -29,8 +29,8 @@ PLAN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "plans")
 SORT = {"split": 1, "thm2": 2, "bitonic": 3, "merge": 4, "naive": 15}
 KNOBS = {
     "sort_plan_4096": ([SORT["bitonic"], SORT["merge"], SORT["split"]], SORT["bitonic"]),
-    "sort_plan_8192": ([SORT["split"], SORT["merge"]], SORT["split"]),
-    "sort_plan_16384": ([SORT["split"], SORT["merge"]], SORT["split"]),
+    "sort_plan_8192": ([SORT["merge"], SORT["split"]], SORT["merge"]),
+    "sort_plan_16384": ([SORT["merge"], SORT["split"]], SORT["merge"]),
     "merge_pack": ([1, 0], 1),
     "partition_waves_4096": ([106, 8, 108, 104, 16, 4], 106),
     "permute_variant": ([0, 1, 2], 0),
@@ -108,8 +108,8 @@ def tune(quick: bool = False, log=print) -> dict:
     plan, timings, baseline = {}, {}, {}
 
     def choose(knob: str, run_for: Callable[[int], Callable[[], object]], n_items: int,
-               set_knob: bool, default_after: Optional[int] = None):
-        cands, default = KNOBS[knob]
+               set_knob: bool):
+        cands, _ = KNOBS[knob]
         best, res = None, {}
         for v in cands:
             if set_knob:

@@ -40,7 +40,7 @@ int sched_of(uint32_t flags) { return (int)((flags >> 8) & 0xFu); }
 // Schedules TS_SCHED_AUTO picks for tile_sort, by max_tile_len up to 4096, 8192 and
 // 16384 (longer tiles always take the merge schedule).  Set by the autotuner through
 // ts_tune("sort_plan_<len>", schedule).
-int g_sort_plan[3] = {TS_SCHED_BITONIC, TS_SCHED_SPLIT, TS_SCHED_SPLIT};
+int g_sort_plan[3] = {TS_SCHED_BITONIC, TS_SCHED_MERGE, TS_SCHED_MERGE};
 
 int resolve_sort_sched(uint32_t flags, int64_t max_len) {
     const int s = sched_of(flags);

@@ -104,6 +104,6 @@ def test_tune_knob_validation(lib):
     assert lib.ts_tune(b"sort_plan_4096", 7) == 1
     assert lib.ts_tune(b"merge_pack", 2) == 1
     assert lib.ts_tune(b"no_such_knob", 0) == 1
-    assert lib.ts_tune(b"sort_plan_16384", 4) == 0
-    assert lib.ts_tune(b"sort_plan_16384", 1) == 0         # back to the default
+    assert lib.ts_tune(b"sort_plan_16384", 1) == 0
+    assert lib.ts_tune(b"sort_plan_16384", 4) == 0         # back to the default
     assert lib.ts_tune(b"merge_pack", 1) == 0
