@@ -191,9 +191,10 @@ ts_status ts_lds_probe(const uint32_t* lane_words, int op, int width, int iters,
 
 /* Override a tuning knob of the kernel-selection table (used by the autotuner).
    Knobs: "partition_waves_4096" (1, 2, 4, 8 or 16 waves per workgroup; 104 and 108:
-   4 or 8 waves with registers capped so four workgroups fit on a CU; 118: 8 waves
-   without prefetching the next tile; 204, 208, 216:
-   two tiles per workgroup with 4, 8 or 16 waves); "permute_variant" (0: registers as
+   4 or 8 waves with registers capped so four workgroups fit on a CU; 110: 8 waves,
+   five workgroups per CU; 106 / 116: 8 waves, three workgroups per CU, with / without
+   loading the next tile during the current one; 118: 8 waves without prefetching the
+   next tile; 204, 208, 216: two tiles per workgroup with 4, 8 or 16 waves); "permute_variant" (0: registers as
    the compiler chooses; 1: registers capped for more workgroups per CU; 2: 8-wave
    workgroups for 8192-item tiles); "merge_pack" (1: tiles of up to 2048 keys share a
    wavefront in the merge schedule, 0: one tile per wavefront); "sort_plan_4096",

@@ -32,7 +32,7 @@ KNOBS = {
     "sort_plan_8192": ([SORT["merge"], SORT["split"]], SORT["merge"]),
     "sort_plan_16384": ([SORT["merge"], SORT["split"]], SORT["merge"]),
     "merge_pack": ([1, 0], 1),
-    "partition_waves_4096": ([106, 8, 108, 104, 16, 4], 106),
+    "partition_waves_4096": ([106, 116, 108, 110, 8, 104], 106),
     "permute_variant": ([0, 1, 2], 0),
 }
 

@@ -312,11 +312,11 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
 ts_status ts_tune(const char* knob, int value) {
     if (knob == nullptr) return fail(TS_ERR_INVALID, "ts_tune: knob is NULL");
     if (std::strcmp(knob, "partition_waves_4096") == 0) {
-        static const int ok[] = {1, 2, 4, 8, 16, 104, 106, 108, 118, 204, 208, 216};
+        static const int ok[] = {1, 2, 4, 8, 16, 104, 106, 108, 110, 116, 118, 204, 208, 216};
         bool found = false;
         for (int v : ok) found |= (v == value);
         if (!found)
-            return fail(TS_ERR_INVALID, "ts_tune: partition_waves_4096 must be one of 1, 2, 4, 8, 16, 104, 106, 108, 118, 204, 208, 216");
+            return fail(TS_ERR_INVALID, "ts_tune: partition_waves_4096 must be one of 1, 2, 4, 8, 16, 104, 106, 108, 110, 116, 118, 204, 208, 216");
         ts::set_partition_waves(value);
         return TS_OK;
     }

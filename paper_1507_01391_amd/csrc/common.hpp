@@ -103,6 +103,16 @@ TS_DEV void lds_store(T* base, uint32_t byte_off, T v) {
     *(T*)((char*)base + byte_off) = v;
 }
 
+// A 64-bit LDS load kept whole.  When only one half of a loaded 64-bit slot is used,
+// the compiler narrows the load to 32 bits at a two-word stride, which puts lanes L
+// and L+16 of a 32-lane phase on one bank; this keeps the conflict-free 64-bit access.
+template <typename T>
+TS_DEV uint64_t lds_load_u64_whole(const T* base, uint32_t byte_off) {
+    uint64_t v = *(const uint64_t*)((const char*)base + byte_off);
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 TS_DEV uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
 TS_DEV uint32_t lo32(uint64_t x) { return (uint32_t)x; }
 TS_DEV uint64_t pack(uint32_t hi, uint32_t lo) { return ((uint64_t)hi << 32) | lo; }

@@ -77,25 +77,29 @@ TS_DEV void issue_tile_load(const SplitArgs& a, const int64_t* __restrict__ offs
     load_columns<CPW>(a.pay_in, a.pay_es, o, a.has_pay ? nn : 0, w * CPW, lane, L.pay, offs);
 }
 
-template <int NW, int CAP, int WPE, int MODE>
+template <int NW, int CAP, int WPE, int MODE, int PF = -1>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
     constexpr int CPW = CAP / 64 / NW;  // columns per wave
-    // Narrow waves have room to load the next tile during this one; wide ones load
-    // each tile when they start it (WPE < 0: never prefetch).
-    constexpr bool PREFETCH = CPW <= 16 && WPE == 0;
+    // Whether the next tile's loads are issued before this tile is split (PF = 1 / 0).
+    // By default narrow, uncapped waves prefetch and the rest load each tile when they
+    // start it (WPE < 0: never prefetch).
+    constexpr bool PREFETCH = PF >= 0 ? PF == 1 : (CPW <= 16 && WPE == 0);
     __shared__ uint64_t A[CAP];
     __shared__ int wz[NW];
-    const int lane = lane_id();
+    const int lane0 = lane_id();
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lmask = (MODE == 0) ? (1u << a.nbits) - 1u : 0xFFFFFFFFu;
     const bool has_pay = a.has_pay != 0;
 
     TileLoad<CPW> L;
     int64_t t = blockIdx.x;
-    issue_tile_load<CPW, CAP>(a, offs, t, w, lane, L);
+    issue_tile_load<CPW, CAP>(a, offs, t, w, lane0, L);
 
     for (; t < a.num_tiles; t += gridDim.x) {
+        // lane-derived values (positions, addresses) are recomputed per tile rather
+        // than hoisted out of the tile loop and kept live across it
+        const int lane = (int)opaque((uint32_t)lane0);
         const int64_t o = L.o;
         const int n = L.n;
         if (n == -2) {  // longer than this kernel's capacity: skip and flag
@@ -374,9 +378,9 @@ hipError_t launch_split2(const SplitArgs& a, const int64_t* offs, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int NW, int CAP, int WPE = 0, int MODE = 0>
+template <int NW, int CAP, int WPE = 0, int MODE = 0, int PF = -1>
 hipError_t launch_split(const SplitArgs& a, const int64_t* offs, hipStream_t s) {
-    auto kern = split_kernel<NW, CAP, WPE, MODE>;
+    auto kern = split_kernel<NW, CAP, WPE, MODE, PF>;
     const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, offs);
     return hipGetLastError();
@@ -416,9 +420,11 @@ hipError_t launch_partition_split(const PartitionArgs& p, int64_t max_len, hipSt
             case 4: return launch_split<4, 4096>(a, o, s);
             case 16: return launch_split<16, 4096>(a, o, s);
             case 108: return launch_split<8, 4096, 8>(a, o, s);   // 8 waves, 4 workgroups per CU
+            case 110: return launch_split<8, 4096, 10>(a, o, s);  // 8 waves, 5 workgroups per CU
             case 104: return launch_split<4, 4096, 4>(a, o, s);   // 4 waves, 4 workgroups per CU
             case 118: return launch_split<8, 4096, -1>(a, o, s);  // 8 waves, no prefetch
-            case 106: return launch_split<8, 4096, 6>(a, o, s);   // 8 waves, three workgroups per CU
+            case 106: return launch_split<8, 4096, 6, 0, 1>(a, o, s);  // 3 workgroups per CU, prefetch
+            case 116: return launch_split<8, 4096, 6, 0, 0>(a, o, s);  // 3 workgroups per CU
             case 208: return launch_split2<8, 4096, 0>(a, o, s);  // two tiles per workgroup
             case 204: return launch_split2<4, 4096, 0>(a, o, s);
             case 216: return launch_split2<16, 4096, 0>(a, o, s);

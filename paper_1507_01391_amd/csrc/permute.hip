@@ -63,7 +63,7 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
             R::route(A, wz, e, w, lane);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
-                const uint64_t x = lds_load(A, own_base + 512u * j);
+                const uint64_t x = lds_load_u64_whole(A, own_base + 512u * j);
                 if (a.validate) flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)(64 * (w * CPW + j) + lane), ERR_BAD_PERM);
                 dst[j] = lo32(x);  // inv[q] for q = 64k + l
             }
@@ -72,16 +72,20 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
 
 #pragma unroll 1
         for (uint32_t c = 0; c < a.pay.channels; ++c) {
+            // per-column addresses are recomputed per channel instead of being kept
+            // live (or spilled) across the whole channel loop
+            const int lc = (int)opaque((uint32_t)lane);
+            const uint32_t own_c = (uint32_t)lc * 8u + (uint32_t)(w * CPW * 512);
             const int64_t cbase = (int64_t)c * a.pay.cs;
             uint32_t xv[CPW];
-            load_columns<CPW>(a.pay.in + cbase, a.pay.es, o, n, w * CPW, lane, xv, offs);
+            load_columns<CPW>(a.pay.in + cbase, a.pay.es, o, n, w * CPW, lc, xv, offs);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) e[j] = pack(dst[j], xv[j]);
             R::route(A, wz, e, w, lane);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
-                const int v = 64 * (w * CPW + j) + lane;
-                const uint64_t x = lds_load(A, own_base + 512u * j);
+                const int v = 64 * (w * CPW + j) + lc;
+                const uint64_t x = lds_load_u64_whole(A, own_c + 512u * j);
                 if (a.validate && c == 0 && !gather)
                     flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)v, ERR_BAD_PERM);
                 if (v < n) store_item(a.pay.out + cbase, a.pay.es, o, v, lo32(x));

@@ -59,7 +59,7 @@ def test_large_tiles(ts, oracle, schedule, cap):
     run_and_compare(ts, oracle, labels, payload, off, 64, schedule, max_len=cap)
 
 
-@pytest.mark.parametrize("waves", [1, 2, 4, 8, 16, 104, 106, 108, 118, 204, 208, 216])
+@pytest.mark.parametrize("waves", [1, 2, 4, 8, 16, 104, 106, 108, 110, 116, 118, 204, 208, 216])
 def test_wave_count_variants(ts, oracle, waves):
     labels, payload, off = inputs.partition(seed=30 + waves, num_tiles=40, n=4096)
     prev = ts.knob("partition_waves_4096", 106)
