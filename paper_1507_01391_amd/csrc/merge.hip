@@ -19,7 +19,7 @@
 //   1. clear the work counters (a fill kernel, so the sequence stays capturable);
 //   2. bin: one thread per tile appends the tile to a packing bin or its pieces to the
 //      piece list, and its output pieces to the list of every merge round it needs;
-//   3. sort: one persistent launch over all bins and pieces;
+//   3. sort: one persistent launch per packing bin and one for the pieces;
 //   4. per merge round: co-rank search (one thread per output piece), then the merge.
 // The last store of every tile writes keys, the permutation and the payload, gathered
 // from the input by the permutation.
@@ -79,8 +79,6 @@ TS_DEV void wave_append(uint32_t* counter, uint64_t* list, int64_t cap, uint32_t
     for (uint32_t j = 0; j < cnt && (int64_t)(start + j) < cap; ++j) list[start + j] = entry(tile, j);
 }
 
-// Bins: 0 .. 3 pack P = 8, 4, 2, 1 tiles per wavefront (tiles of at most 4096 / P keys).
-TS_DEV int pack_of(int bin) { return 8 >> bin; }
 
 __global__ __launch_bounds__(256) void merge_bin_kernel(MergeArgs a) {
     const int lane = lane_id();
@@ -121,15 +119,65 @@ __global__ __launch_bounds__(256) void merge_bin_kernel(MergeArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
-// Final store of one item of a tile: key, permutation and payload gathered by it.
-TS_DEV void store_final(const SortArgs& s, int64_t o, int64_t rank, uint64_t c) {
-    const uint32_t key = comp_key(c);
-    const uint32_t pos = comp_pos(c);
-    if (s.keys_out) s.keys_out[o + rank] = s.f32 ? ordered_to_f32(key) : key;
-    if (s.perm_out) s.perm_out[o + rank] = (int32_t)pos;
+// Final stores of registers c0 .. c0+NC-1 of one tile: register c0 + c of lane L holds
+// rank rb + 64 c + L, valid below `nvalid`.  Keys and positions are written straight
+// from the composites; the payload is gathered through the positions 16 registers at a
+// time, every load of a group issued before any is used (a load per register inside
+// its own branch would wait for each one in turn).
+template <int NC>
+TS_DEV void store_final_regs(const SortArgs& s, int64_t o, int64_t rb, int nvalid,
+                             const uint64_t (&v)[R], int c0, int lane) {
+    const int ln = (int)opaque((uint32_t)lane);
     const PayloadRef& p = s.pay;
-    for (uint32_t ch = 0; ch < p.channels; ++ch)
-        p.out[(o + rank) * p.es + (int64_t)ch * p.cs] = p.in[(o + (int64_t)pos) * p.es + (int64_t)ch * p.cs];
+    // keys and positions, addressed as one wave-uniform pointer plus 32-bit byte
+    // offsets; afterwards only the positions stay live
+    uint32_t* kb = s.keys_out ? s.keys_out + o + rb : nullptr;
+    int32_t* pb = s.perm_out ? s.perm_out + o + rb : nullptr;
+    uint32_t pos_of[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int q = 64 * c + ln;
+        const uint32_t key = comp_key(v[c0 + c]);
+        pos_of[c] = comp_pos(v[c0 + c]);
+        if (q < nvalid) {
+            if (kb) *(uint32_t*)((char*)kb + (uint32_t)q * 4u) = s.f32 ? ordered_to_f32(key) : key;
+            if (pb) *(int32_t*)((char*)pb + (uint32_t)q * 4u) = (int32_t)pos_of[c];
+        }
+    }
+    if (p.channels == 0) return;
+    // (positions are below 2^20, so with at most 1024 words per element every payload
+    // offset inside the tile fits in 32 bits)
+    const bool narrow = p.es <= 1024;
+    constexpr int G = NC < 16 ? NC : 16;
+#pragma unroll 1
+    for (uint32_t ch = 0; ch < p.channels; ++ch) {
+        const int lc = (int)opaque((uint32_t)ln);
+        const uint32_t* pin = p.in + (int64_t)ch * p.cs + o * p.es;           // tile item 0
+        uint32_t* pout = p.out + (int64_t)ch * p.cs + (o + rb) * p.es;        // rank rb
+        const uint32_t es4 = (uint32_t)p.es * 4u;
+#pragma unroll
+        for (int g = 0; g < NC; g += G) {
+            uint32_t pv[G];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int q = 64 * (g + j) + lc;
+                if (narrow) {
+                    const uint32_t off = (q < nvalid) ? pos_of[g + j] * es4 : 0u;
+                    pv[j] = *(const uint32_t*)((const char*)pin + off);
+                } else {
+                    pv[j] = *((q < nvalid) ? pin + (int64_t)pos_of[g + j] * p.es : pin);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int q = 64 * (g + j) + lc;
+                if (q < nvalid) {
+                    if (narrow) *(uint32_t*)((char*)pout + (uint32_t)q * es4) = pv[j];
+                    else pout[(int64_t)q * p.es] = pv[j];
+                }
+            }
+        }
+    }
 }
 
 // Tile of bin entry e (or none past the bin's count): offset and length, wave-uniform.
@@ -190,12 +238,7 @@ TS_DEV void store_packed(const uint64_t (&v)[R], const MergeArgs& a, int bin, ui
         int64_t o;
         int n;
         bin_tile(a, bin, cnt, item * P + sl, o, n);
-        const int ln = (int)opaque((uint32_t)lane);
-#pragma unroll
-        for (int j = 0; j < CPS; ++j) {
-            const int r = 64 * j + ln;  // rank within the tile
-            if (r < n) store_final(a.s, o, r, v[sl * CPS + j]);
-        }
+        store_final_regs<CPS>(a.s, o, 0, n, v, sl * CPS, lane);
     }
 }
 
@@ -211,62 +254,47 @@ TS_DEV void piece_range(const MergeArgs& a, uint64_t e, int64_t& o, int& n, uint
     n = (int)(rem < K ? rem : K);
 }
 
+// KIND 0 .. 3: packing bin KIND (8, 4, 2, 1 tiles per wavefront); KIND 4: pieces of
+// long tiles.  One launch per kind keeps every kernel straight-line code.
+template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 void merge_sort_kernel(MergeArgs a) {
     __shared__ uint32_t A[MOVE_WORDS];
-    uint32_t cnt[5], start[6];
-    start[0] = 0;
-#pragma unroll
-    for (int b = 0; b < 5; ++b) {
-        cnt[b] = uniform(a.counters[b]);
-        if (b == 4 && cnt[b] > (uint32_t)a.cap) cnt[b] = (uint32_t)a.cap;
-        const uint32_t items = (b < 4) ? (cnt[b] + pack_of(b) - 1) / pack_of(b) : cnt[b];
-        start[b + 1] = start[b] + items;
-    }
-    for (uint32_t w = blockIdx.x; w < start[5]; w += gridDim.x) {
+    constexpr int P = KIND < 4 ? (8 >> KIND) : 1;
+    uint32_t cnt = uniform(a.counters[KIND]);
+    if (KIND == 4 && cnt > (uint32_t)a.cap) cnt = (uint32_t)a.cap;
+    const uint32_t items = (cnt + P - 1) / P;
+    for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
         const int lane = (int)opaque((uint32_t)lane_id());
-        int kind = 4;
-        uint32_t item = w - start[4];
-        if (w < start[1]) { kind = 0; item = w; }
-        else if (w < start[2]) { kind = 1; item = w - start[1]; }
-        else if (w < start[3]) { kind = 2; item = w - start[2]; }
-        else if (w < start[4]) { kind = 3; item = w - start[3]; }
         uint64_t v[R];
-        switch (kind) {
-            case 0: load_packed<8>(A, v, a, 0, cnt[0], item, lane); break;
-            case 1: load_packed<4>(A, v, a, 1, cnt[1], item, lane); break;
-            case 2: load_packed<2>(A, v, a, 2, cnt[2], item, lane); break;
-            case 3: load_packed<1>(A, v, a, 3, cnt[3], item, lane); break;
-            default: {
-                int64_t o;
-                int n;
-                uint32_t base;
-                piece_range(a, a.pieces[item], o, n, base);
-                stage_keys<64>(A, a.s, o, n, 0, lane);
+        if constexpr (KIND < 4) {
+            load_packed<P>(A, v, a, KIND, cnt, item, lane);
+        } else {
+            int64_t o;
+            int n;
+            uint32_t base;
+            piece_range(a, a.pieces[item], o, n, base);
+            stage_keys<64>(A, a.s, o, n, 0, lane);
 #pragma unroll
-                for (int c = 0; c < R; ++c) {
-                    const uint32_t i = (uint32_t)(64 * c + lane);
-                    v[c] = make_comp(0u, lds_load(A, i * 4u), base + i);
-                }
+            for (int c = 0; c < R; ++c) {
+                const uint32_t i = (uint32_t)(64 * c + lane);
+                v[c] = make_comp(0u, lds_load(A, i * 4u), base + i);
             }
         }
         bitonic_sort4096(A, v, lane);
-        switch (kind) {
-            case 0: store_packed<8>(v, a, 0, cnt[0], item, lane); break;
-            case 1: store_packed<4>(v, a, 1, cnt[1], item, lane); break;
-            case 2: store_packed<2>(v, a, 2, cnt[2], item, lane); break;
-            case 3: store_packed<1>(v, a, 3, cnt[3], item, lane); break;
-            default: {
-                int64_t o;
-                int n;
-                uint32_t base;
-                piece_range(a, a.pieces[item], o, n, base);
-                const int ln = (int)opaque((uint32_t)lane);
+        if constexpr (KIND < 4) {
+            store_packed<P>(v, a, KIND, cnt, item, lane);
+        } else {
+            int64_t o;
+            int n;
+            uint32_t base;
+            piece_range(a, a.pieces[item], o, n, base);
+            const int ln = (int)opaque((uint32_t)lane);
+            uint64_t* rb = a.run0 + o;
 #pragma unroll
-                for (int c = 0; c < R; ++c) {
-                    const int r = 64 * c + ln;
-                    if (r < n) a.run0[o + r] = v[c];
-                }
+            for (int c = 0; c < R; ++c) {
+                const int r = 64 * c + ln;
+                if (r < n) *(uint64_t*)((char*)rb + (uint32_t)r * 8u) = v[c];
             }
         }
     }
@@ -327,6 +355,10 @@ __global__ __launch_bounds__(256) void merge_corank_kernel(MergeArgs a, int r) {
     }
 }
 
+// LAST = true handles the output pieces of tiles that this round finishes (final keys,
+// permutation and payload), LAST = false the others (runs for the next round); the two
+// are separate launches so that each is a straight-line kernel.
+template <bool LAST>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 void merge_round_kernel(MergeArgs a, int r) {
     __shared__ uint32_t A[MOVE_WORDS];
@@ -336,8 +368,9 @@ void merge_round_kernel(MergeArgs a, int r) {
     const uint64_t* in = (r & 1) ? a.run1 : a.run0;
     uint64_t* out_run = (r & 1) ? a.run0 : a.run1;
     for (uint32_t w = blockIdx.x; w < cnt; w += gridDim.x) {
-        const int lane = (int)opaque((uint32_t)lane_id());
         const PieceGeom g = piece_geom(a, list[w], r);
+        if (g.last != LAST) continue;
+        const int lane = (int)opaque((uint32_t)lane_id());
         const int64_t i0 = uniform((uint32_t)cr[2 * (int64_t)w]);
         const int64_t i1 = uniform((uint32_t)cr[2 * (int64_t)w + 1]);
         const int la = (int)(i1 - i0);                        // from run A
@@ -363,12 +396,8 @@ void merge_round_kernel(MergeArgs a, int r) {
         const int ln = (int)opaque((uint32_t)lane);
         const int64_t ob = g.ps + g.d0;  // tile position of output rank 0
         const int nout = (int)(g.d1 - g.d0);
-        if (g.last) {
-#pragma unroll
-            for (int c = 0; c < R; ++c) {
-                const int q = 64 * c + ln;
-                if (q < nout) store_final(a.s, g.o, ob + q, v[c]);
-            }
+        if (LAST) {
+            store_final_regs<R>(a.s, g.o, ob, nout, v, 0, lane);
         } else {
             uint64_t* ob_ptr = out_run + g.o + ob;
 #pragma unroll
@@ -442,18 +471,34 @@ hipError_t launch_sort_merge(const SortArgs& s, int64_t total_len, int64_t max_l
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {
-        const int g = persistent_grid((const void*)merge_sort_kernel, 64, 0, s.num_tiles + L.cap);
-        hipLaunchKernelGGL(merge_sort_kernel, dim3(g), dim3(64), 0, st, a);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // pieces first (the longest chains of work), then the packing bins
+        const void* kinds[5] = {(const void*)merge_sort_kernel<4>, (const void*)merge_sort_kernel<3>,
+                                (const void*)merge_sort_kernel<2>, (const void*)merge_sort_kernel<1>,
+                                (const void*)merge_sort_kernel<0>};
+        const int64_t bound[5] = {L.cap, s.num_tiles, s.num_tiles, s.num_tiles, s.num_tiles};
+        for (int k = 0; k < 5; ++k) {
+            const int g = persistent_grid(kinds[k], 64, 0, bound[k]);
+            switch (k) {
+                case 0: hipLaunchKernelGGL(merge_sort_kernel<4>, dim3(g), dim3(64), 0, st, a); break;
+                case 1: hipLaunchKernelGGL(merge_sort_kernel<3>, dim3(g), dim3(64), 0, st, a); break;
+                case 2: hipLaunchKernelGGL(merge_sort_kernel<2>, dim3(g), dim3(64), 0, st, a); break;
+                case 3: hipLaunchKernelGGL(merge_sort_kernel<1>, dim3(g), dim3(64), 0, st, a); break;
+                default: hipLaunchKernelGGL(merge_sort_kernel<0>, dim3(g), dim3(64), 0, st, a); break;
+            }
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     for (int r = 0; r < L.rounds; ++r) {
         int64_t gc = (L.cap + 255) / 256;
         if (gc > 2048) gc = 2048;
         hipLaunchKernelGGL(merge_corank_kernel, dim3((unsigned)gc), dim3(256), 0, st, a, r);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int g = persistent_grid((const void*)merge_round_kernel, 64, 0, L.cap);
-        hipLaunchKernelGGL(merge_round_kernel, dim3(g), dim3(64), 0, st, a, r);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int last = 0; last < 2; ++last) {
+            auto kern = last ? merge_round_kernel<true> : merge_round_kernel<false>;
+            const int g = persistent_grid((const void*)kern, 64, 0, L.cap);
+            hipLaunchKernelGGL(kern, dim3(g), dim3(64), 0, st, a, r);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
