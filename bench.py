@@ -215,7 +215,10 @@ def bench_c1(torch, ts, inputs):
 
 
 def bench_c3(args, torch, ts, inputs):
-    """fwd (scatter) + bwd (gather) permutation of 16384 tiles x 8192 fp32."""
+    """fwd + bwd permutation of 16384 tiles x 8192 fp32: forward y[pi[i]] = x[i], backward
+    dx[i] = dy[pi[i]] -- the conflict-free path writes pi^-1 during the forward routing
+    and runs the backward as a scatter by it (what autograd.Permute does); the naive
+    form scatters forward and gathers backward, one LDS pass each."""
     T = args.tiles3
     x, pi, g, off = inputs.permutation(num_tiles=T, n=8192)
     dx = torch.from_numpy(x).cuda()
@@ -224,16 +227,41 @@ def bench_c3(args, torch, ts, inputs):
     doff = torch.from_numpy(off).cuda()
     y = torch.empty_like(dx)
     gx = torch.empty_like(dx)
+    inv = torch.empty_like(dpi)
+    n = T * 8192
     out = {}
-    for sched in ("split", "naive"):
-        def fwd_bwd():
-            ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y, schedule=sched)
-            ts.tile_permute(dg, dpi, "gather", doff, max_tile_len=8192, out=gx, schedule=sched)
-        log(f"[bench] C3 fwd+bwd permute ({sched}) ...")
-        w, m, _ = timed_launches(fwd_bwd, 10, 3, torch)
-        out[f"c3_permute_fwd_bwd_GBps_{sched}"] = 2 * PERMUTE_BYTES_PER_ELEM * T * 8192 / (m / 1e3) / 1e9
+
+    def split_fwd_bwd():
+        ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y, inv_out=inv)
+        ts.tile_permute(dg, inv, "scatter", doff, max_tile_len=8192, out=gx)
+
+    def split_scatter_gather():
+        ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y)
+        ts.tile_permute(dg, dpi, "gather", doff, max_tile_len=8192, out=gx)
+
+    def naive_fwd_bwd():
+        ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y, schedule="naive")
+        ts.tile_permute(dg, dpi, "gather", doff, max_tile_len=8192, out=gx, schedule="naive")
+
+    for name, fn in (("split", split_fwd_bwd), ("split_scatter_plus_gather", split_scatter_gather),
+                     ("naive", naive_fwd_bwd)):
+        log(f"[bench] C3 fwd+bwd permute ({name}) ...")
+        w, m, _ = timed_launches(fn, 10, 3, torch)
+        out[f"c3_permute_fwd_bwd_GBps_{name}"] = 2 * PERMUTE_BYTES_PER_ELEM * n / (m / 1e3) / 1e9
+    # parity of the conflict-free fwd + bwd on sampled tiles
+    split_fwd_bwd()
+    yh, gh = y.cpu().numpy(), gx.cpu().numpy()
+    ok = True
+    for t in np.sort(np.random.default_rng(2).choice(T, size=min(8, T), replace=False)):
+        a, b = int(off[t]), int(off[t + 1])
+        p = pi[a:b]
+        want_y = np.empty(b - a, np.float32)
+        want_y[p] = x[a:b]
+        ok &= bool(np.array_equal(yh[a:b].view(np.uint32), want_y.view(np.uint32)) and
+                   np.array_equal(gh[a:b].view(np.uint32), g[a:b][p].view(np.uint32)))
+    out["c3_parity_sampled_tiles"] = "8 tiles bit-exact" if ok else "MISMATCH"
     out["c3_tiles"] = T
-    del dx, dpi, dg, y, gx
+    del dx, dpi, dg, y, gx, inv
     return out
 
 

@@ -140,12 +140,17 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
  * row i; here the label is the tile-local linear destination).  pi is int32 [N],
  * a permutation of [0, len) inside every tile.
  *   TS_SCATTER: out[pi[i]] = in[i];   TS_GATHER: out[i] = in[pi[i]].
- * in / out use the payload addressing above with `channels` words per item.
+ * in / out use the payload addressing above with `channels` words per item
+ * (channels may be 0 when only inv_out is wanted).
+ *   inv_out : optional int32 [N]: receives the tile-local inverse permutation,
+ *             inv_out[pi[i]] = i, computed by the same routing (no extra pass);
+ *             a later GATHER by pi equals a SCATTER by inv_out, which routes once
+ *             instead of twice.  Must not alias pi or in.
  * Supported tile length: max_tile_len <= 16384.
  */
 ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels,
                        int64_t elem_stride, int64_t chan_stride,
-                       const int32_t* pi, uint32_t direction,
+                       const int32_t* pi, uint32_t direction, int32_t* inv_out,
                        const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
                        uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
 

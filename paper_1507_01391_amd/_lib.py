@@ -51,7 +51,7 @@ def load() -> ctypes.CDLL:
     S = ctypes.c_int
     lib.tile_sort.argtypes = [P, P, P, P, U32, I64, I64, P, P, I64, I64, I64, U32, P, SZ, P]
     lib.tile_partition.argtypes = [P, P, P, P, U32, I64, I64, U32, P, P, I64, I64, U32, P, SZ, P]
-    lib.tile_permute.argtypes = [P, P, U32, I64, I64, P, U32, P, I64, I64, U32, P, SZ, P]
+    lib.tile_permute.argtypes = [P, P, U32, I64, I64, P, U32, P, P, I64, I64, U32, P, SZ, P]
     for f in ("tile_sort", "tile_partition", "tile_permute"):
         getattr(lib, f).restype = S
     lib.ts_workspace_bytes.argtypes = [ctypes.c_int, U32, I64, I64, I64, U32]

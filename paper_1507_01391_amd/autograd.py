@@ -4,7 +4,9 @@ Both backward passes move the upstream gradient through the inverse of the
 forward permutation with the same conflict-free tile kernels; indices and keys
 stay exact integers throughout.
 
-* ``Permute``:  y = scatter(x, pi), i.e. y[pi[i]] = x[i]; dx[i] = dy[pi[i]] (gather).
+* ``Permute``:  y = scatter(x, pi), i.e. y[pi[i]] = x[i]; dx[i] = dy[pi[i]], computed as
+  a scatter by pi^-1, which the forward routing writes out at no extra pass (a direct
+  gather would route twice).
 * ``SortWithPayload``: keys are fp32, sorted ascending through the order-preserving
   bit map (stable; -0 before +0); payload_out[:, k] = payload[:, perm[k]] and
   sorted_keys[k] = keys[perm[k]]; backward scatters: dp[:, perm[k]] = dpo[:, k].
@@ -19,15 +21,16 @@ from . import ops
 class Permute(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, pi, offsets, max_tile_len=None):
-        y = ops.tile_permute(x.contiguous(), pi, "scatter", offsets, max_tile_len)
-        ctx.save_for_backward(pi, offsets)
+        inv = torch.empty_like(pi)
+        y = ops.tile_permute(x.contiguous(), pi, "scatter", offsets, max_tile_len, inv_out=inv)
+        ctx.save_for_backward(inv, offsets)
         ctx.max_tile_len = max_tile_len
         return y
 
     @staticmethod
     def backward(ctx, gy):
-        pi, offsets = ctx.saved_tensors
-        gx = ops.tile_permute(gy.contiguous(), pi, "gather", offsets, ctx.max_tile_len)
+        inv, offsets = ctx.saved_tensors
+        gx = ops.tile_permute(gy.contiguous(), inv, "scatter", offsets, ctx.max_tile_len)
         return gx, None, None, None
 
 

@@ -203,7 +203,7 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
 }
 
 ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int64_t elem_stride,
-                       int64_t chan_stride, const int32_t* pi, uint32_t direction,
+                       int64_t chan_stride, const int32_t* pi, uint32_t direction, int32_t* inv_out,
                        const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
                        uint32_t flags, void* workspace, size_t workspace_bytes, void* stream) {
     ts_status st = check_common(tile_offsets, num_tiles, max_tile_len, workspace, workspace_bytes);
@@ -211,10 +211,15 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int
     if (direction != TS_SCATTER && direction != TS_GATHER)
         return fail(TS_ERR_INVALID, "tile_permute: direction must be TS_SCATTER or TS_GATHER");
     if (num_tiles > 0 && pi == nullptr) return fail(TS_ERR_INVALID, "tile_permute: pi is NULL");
-    if (channels == 0) return TS_OK;
-    if (in == nullptr || out == nullptr) return fail(TS_ERR_INVALID, "tile_permute: in/out is NULL");
-    st = check_payload(in, out, channels, elem_stride, chan_stride, true);
-    if (st != TS_OK) return st;
+    if (channels == 0 && inv_out == nullptr) return TS_OK;
+    if (channels > 0) {
+        if (in == nullptr || out == nullptr) return fail(TS_ERR_INVALID, "tile_permute: in/out is NULL");
+        st = check_payload(in, out, channels, elem_stride, chan_stride, true);
+        if (st != TS_OK) return st;
+    }
+    if (inv_out != nullptr && ((const void*)inv_out == (const void*)pi ||
+                               (const void*)inv_out == (const void*)in))
+        return fail(TS_ERR_INVALID, "tile_permute: inv_out aliases pi or in");
     if (max_tile_len > ts::permute_split_capacity())
         return fail(TS_ERR_UNSUPPORTED, "tile_permute: max_tile_len %lld > %lld",
                     (long long)max_tile_len, (long long)ts::permute_split_capacity());
@@ -222,6 +227,7 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int
     a.pay = ts::PayloadRef{in, out, channels, elem_stride, chan_stride};
     a.pi = pi;
     a.direction = direction;
+    a.inv_out = inv_out;
     a.offsets = tile_offsets;
     a.num_tiles = num_tiles;
     a.validate = (flags & TS_FLAG_VALIDATE) ? 1u : 0u;

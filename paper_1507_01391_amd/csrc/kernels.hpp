@@ -40,6 +40,7 @@ struct PermuteArgs {
     PayloadRef pay;     // in / out with channels and strides
     const int32_t* pi;
     uint32_t direction;
+    int32_t* inv_out;   // optional: receives pi^-1 (inv_out[pi[i]] = i)
     const int64_t* offsets;
     int64_t num_tiles;
     uint32_t validate;

@@ -152,6 +152,13 @@ __global__ __launch_bounds__(NW * 64) void permute_naive_kernel(PermuteArgs a) {
         load_columns<CPW>(a.pi, 1, o, n, w * CPW, lane, pidx, a.offsets);
 #pragma unroll
         for (int j = 0; j < CPW; ++j) pidx[j] &= (CAP - 1);
+        if (a.inv_out) {  // inv[pi[i]] = i, a direct scatter to global memory
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int i = 64 * (w * CPW + j) + lane;
+                if (i < n) a.inv_out[o + pidx[j]] = i;
+            }
+        }
         for (uint32_t c = 0; c < a.pay.channels; ++c) {
             const int64_t cb = (int64_t)c * a.pay.cs;
             uint32_t xv[CPW];

@@ -6,6 +6,10 @@
 //            leaves inv[q] (the output slot that wants in[q]) at every slot q; then
 //            (in[q], destination inv[q]) is routed.  The first routing is shared by
 //            all payload channels.
+// Items carry the source index beside the destination (destination in the low 16
+// bits of the high word, source in the high 16), so either direction can also write
+// the inverse permutation at no extra routing: a scatter's caller can then undo it
+// with another scatter instead of a two-routing gather.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "route.hpp"
@@ -63,22 +67,32 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
             R::route(A, wz, e, w, lane);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
+                const int q = 64 * (w * CPW + j) + lane;
                 const uint64_t x = lds_load_u64_whole(A, own_base + 512u * j);
-                if (a.validate) flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)(64 * (w * CPW + j) + lane), ERR_BAD_PERM);
+                if (a.validate) flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)q, ERR_BAD_PERM);
                 dst[j] = lo32(x);  // inv[q] for q = 64k + l
+                if (a.inv_out && q < n) store_item(a.inv_out, 1, o, q, (int32_t)dst[j]);
             }
             __syncthreads();  // A is reused by the next routing
+        } else {
+            // the source index rides above the destination (for inv_out)
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) dst[j] |= (uint32_t)(64 * (w * CPW + j) + lane) << 16;
         }
 
+        // a scatter asked only for the inverse still routes once (with no payload)
+        const uint32_t nroute = (!gather && a.inv_out && a.pay.channels == 0) ? 1u : a.pay.channels;
 #pragma unroll 1
-        for (uint32_t c = 0; c < a.pay.channels; ++c) {
+        for (uint32_t c = 0; c < nroute; ++c) {
             // per-column addresses are recomputed per channel instead of being kept
             // live (or spilled) across the whole channel loop
             const int lc = (int)opaque((uint32_t)lane);
             const uint32_t own_c = (uint32_t)lc * 8u + (uint32_t)(w * CPW * 512);
             const int64_t cbase = (int64_t)c * a.pay.cs;
+            const bool with_pay = a.pay.channels > 0;
             uint32_t xv[CPW];
-            load_columns<CPW>(a.pay.in + cbase, a.pay.es, o, n, w * CPW, lc, xv, offs);
+            load_columns<CPW>(a.pay.in + (with_pay ? cbase : 0), a.pay.es, o, with_pay ? n : 0, w * CPW,
+                              lc, xv, offs);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) e[j] = pack(dst[j], xv[j]);
             R::route(A, wz, e, w, lane);
@@ -88,7 +102,10 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
                 const uint64_t x = lds_load_u64_whole(A, own_c + 512u * j);
                 if (a.validate && c == 0 && !gather)
                     flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)v, ERR_BAD_PERM);
-                if (v < n) store_item(a.pay.out + cbase, a.pay.es, o, v, lo32(x));
+                if (v < n) {
+                    if (with_pay) store_item(a.pay.out + cbase, a.pay.es, o, v, lo32(x));
+                    if (!gather && c == 0 && a.inv_out) store_item(a.inv_out, 1, o, v, (int32_t)(hi32(x) >> 16));
+                }
             }
             __syncthreads();  // A is reused by the next channel / tile
         }

@@ -76,10 +76,9 @@ struct Router {
                 const uint32_t r0 = count_below(~bal);
                 // zero: seg_base*64 + z + rank0; one: seg_end - 1 - (64 kin - z) - (lane - rank0)
                 const uint32_t z8 = (uint32_t)__builtin_amdgcn_readfirstlane((seg_base * 64 + z) * 8);
-                const uint32_t o8 = (uint32_t)__builtin_amdgcn_readfirstlane(
-                    ((seg_base + seg_cols) * 64 - 1 - 64 * kin + z) * 8);
+                const uint32_t d8 = (uint32_t)__builtin_amdgcn_readfirstlane((seg_cols * 64 - 1 - 64 * kin) * 8);
                 const uint32_t a0 = r0 * 8u + z8;
-                const uint32_t a1 = (r0 * 8u + neg_lane8) + o8;
+                const uint32_t a1 = a0 + neg_lane8 + d8;
                 lds_store(A, select_by_mask(bal, a0, a1), e[j]);
                 z += 64 - popc64(bal);
             }

@@ -128,26 +128,32 @@ def tile_partition(labels: torch.Tensor, payload: Optional[torch.Tensor] = None,
     return labels_out, payload_out, perm_out
 
 
-def tile_permute(x: torch.Tensor, pi: torch.Tensor, direction: str = "scatter", offsets=None,
-                 max_tile_len: Optional[int] = None, schedule: str = "auto",
-                 validate: bool = False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+def tile_permute(x: Optional[torch.Tensor], pi: torch.Tensor, direction: str = "scatter",
+                 offsets=None, max_tile_len: Optional[int] = None, schedule: str = "auto",
+                 validate: bool = False, out: Optional[torch.Tensor] = None,
+                 inv_out: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
     """Apply tile-local permutations: scatter out[pi[i]] = x[i], gather out[i] = x[pi[i]].
-    ``x`` is [N] or [C, N] (channel-planar)."""
-    x = _as_words(x, "x", allow_64=True)
-    n = x.shape[-1]
-    dev = x.device
-    assert pi.dtype == torch.int32 and pi.shape[0] == n and pi.is_cuda
+    ``x`` is [N] or [C, N] (channel-planar), or None when only ``inv_out`` (int32 [N],
+    receives inv_out[pi[i]] = i from the same routing) is wanted.  Returns ``out``."""
+    assert pi.dtype == torch.int32 and pi.is_cuda
+    n = pi.shape[0]
+    dev = pi.device
+    if x is not None:
+        x = _as_words(x, "x", allow_64=True)
+        assert x.shape[-1] == n
+        if out is None:
+            out = torch.empty_like(x)
+    if inv_out is not None:
+        assert inv_out.dtype == torch.int32 and inv_out.shape[0] == n and inv_out.is_contiguous()
     off = _offsets(offsets, n, dev)
     ch, es, cs = _payload_layout(x, n)
-    if out is None:
-        out = torch.empty_like(x)
     d = {"scatter": _lib.TS_SCATTER, "gather": _lib.TS_GATHER}[direction]
     ws = workspace(dev)
     flags = _lib.sched_flags(schedule) | (_lib.TS_FLAG_VALIDATE if validate else 0)
     lib = _lib.load()
-    _lib.check(lib.tile_permute(_ptr(x), _ptr(out), ch, es, cs, _ptr(pi), d, _ptr(off),
-                                off.numel() - 1, _max_len(off, max_tile_len), flags, _ptr(ws),
-                                ws.numel() * 4, _stream(dev)))
+    _lib.check(lib.tile_permute(_ptr(x), _ptr(out), ch, es, cs, _ptr(pi), d, _ptr(inv_out),
+                                _ptr(off), off.numel() - 1, _max_len(off, max_tile_len), flags,
+                                _ptr(ws), ws.numel() * 4, _stream(dev)))
     return out
 
 

@@ -86,3 +86,44 @@ def test_permute_variants(ts, oracle, variant, direction):
         run_and_compare(ts, oracle, x4, pi4, off4, direction, max_len=4096)
     finally:
         ts.tune("permute_variant", prev)
+
+
+def inverse_reference(pi, off):
+    inv = np.empty_like(pi)
+    for t in range(len(off) - 1):
+        a, b = int(off[t]), int(off[t + 1])
+        inv[a + pi[a:b]] = np.arange(b - a, dtype=pi.dtype)
+    return inv
+
+
+@pytest.mark.parametrize("schedule", ["split", "naive"])
+@pytest.mark.parametrize("direction", ["scatter", "gather"])
+@pytest.mark.parametrize("with_payload", [True, False])
+def test_inverse_output(ts, oracle, schedule, direction, with_payload):
+    import torch
+    from tests.gpu_util import dev, host_u32
+    rng = np.random.default_rng(70)
+    sizes = np.array([8192, 0, 1, 65, 4096, 8191, 3000])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pi = np.concatenate([rng.permutation(int(s)) for s in sizes]).astype(np.int32)
+    x = rng.standard_normal((2, off[-1])).astype(np.float32)
+    inv = torch.full((off[-1],), -7, dtype=torch.int32, device="cuda")
+    out = ts.tile_permute(dev(x) if with_payload else None, dev(pi), direction, dev(off),
+                          max_tile_len=8192, schedule=schedule, inv_out=inv)
+    ts.check_device_errors()
+    assert np.array_equal(inv.cpu().numpy(), inverse_reference(pi, off))
+    if with_payload:
+        d = oracle.SCATTER if direction == "scatter" else oracle.GATHER
+        want = oracle.tile_permute(x.view(np.uint32), pi, d, off, nthreads=8)
+        assert np.array_equal(host_u32(out).reshape(want.shape), want)
+
+
+def test_scatter_by_inverse_equals_gather(ts):
+    import torch
+    from tests.gpu_util import dev, host_u32
+    x, pi, _, off = inputs.permutation(seed=71, num_tiles=16, n=8192, family="uniform")
+    inv = torch.empty(pi.shape[0], dtype=torch.int32, device="cuda")
+    ts.tile_permute(None, dev(pi), "scatter", dev(off), inv_out=inv)
+    g1 = ts.tile_permute(dev(x), dev(pi), "gather", dev(off))
+    g2 = ts.tile_permute(dev(x), inv, "scatter", dev(off))
+    assert np.array_equal(host_u32(g1), host_u32(g2))
