@@ -173,9 +173,9 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
                 const uint64_t bj = KEEP ? bal[KEEP ? j : 0] : ballot((hi32(e[j]) >> b) & 1u);
                 const uint32_t r0 = count_below(~bj);  // zeros in lower lanes
                 const uint32_t z8 = (uint32_t)__builtin_amdgcn_readfirstlane(z * 8);
-                const uint32_t d8 = (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 - 64 * k) * 8);
-                const uint32_t a0 = r0 * 8u + z8;           // zero: z + rank0
-                const uint32_t a1 = a0 + neg_lane8 + d8;    // one: N-1-(64k-z)-(lane-rank0)
+                const uint32_t o8 = (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 - 64 * k + z) * 8);
+                const uint32_t a0 = r0 * 8u + z8;                 // zero: z + rank0
+                const uint32_t a1 = (r0 * 8u + neg_lane8) + o8;   // one: N-1-(64k-z)-(lane-rank0)
                 lds_store(A, select_by_mask(bj, a0, a1), e[j]);
                 z += 64 - popc64(bj);
             }
