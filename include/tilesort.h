@@ -74,7 +74,8 @@ enum {
        map (negatives: all bits flipped; non-negatives: sign bit set), so -0 < +0;
        the original bits are written to keys_out */
     TS_FLAG_F32_ORDERED = 1u,
-    /* kernels check labels / pi against the data contract and record violations */
+    /* kernels check labels / pi against the data contract and record violations
+       (labels: every partition schedule; pi: the SPLIT permute schedule) */
     TS_FLAG_VALIDATE = 2u
 };
 
@@ -86,7 +87,7 @@ enum {
     TS_SCHED_THM2 = 2,    /* the paper's Theorem 2 schedule: Lemma 1 on super-rows,
                              column sorts, row sorts (sort and partition) */
     TS_SCHED_BITONIC = 3, /* register row sorts + conflict-free transposes (sort) */
-    TS_SCHED_MERGE = 4,   /* sort of uneven tiles up to 2^20 keys: short tiles packed up to
+    TS_SCHED_MERGE = 4,   /* sort of uneven tiles up to 2^28 keys: short tiles packed up to
                              eight per wavefront, long tiles cut into 4096-key pieces sorted
                              like BITONIC, then rounds of pairwise bitonic merges (sort) */
     TS_SCHED_NAIVE = 15   /* baseline: plain LDS counting / direct scatter, with bank
@@ -108,7 +109,7 @@ enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2 };
  *                         the merge schedule places its runs in the workspace by it,
  *                         and skips (and flags) a tile outside [0, N).
  * Supported tile length: 4096 for THM2 and BITONIC, 16384 for SPLIT and NAIVE,
- * 2^20 for MERGE; a longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the
+ * 2^28 for MERGE; a longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the
  * autotuned plan for max_tile_len up to 4096 / 8192 / 16384 and MERGE beyond.
  * The workspace must hold ts_workspace_bytes(TS_OP_SORT, flags, ...) bytes: the
  * merge schedule needs about 16 bytes per key for its runs and work lists.
@@ -127,6 +128,9 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out,
  * [0, num_classes), 1 <= num_classes <= 64.  Output: items grouped by label in
  * ascending label order, input order kept within a label (stable); labels_out,
  * payload_out and perm_out (optional) follow that order.
+ * Schedules: SPLIT (default; tiles up to 16384), NAIVE, and THM2 / BITONIC, which
+ * partition by sorting the labels with those 4096-key sort schedules (a payload
+ * without perm_out then needs ts_workspace_bytes(TS_OP_PARTITION, flags, ...)).
  */
 ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
                          const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,

@@ -127,6 +127,9 @@ const char* ts_version(void) { return "tilesort 0.1 (gfx950)"; }
 
 size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t total_len,
                           int64_t max_tile_len, uint32_t channels) {
+    if (op == TS_OP_PARTITION && num_tiles > 0 && channels > 0 &&
+        (sched_of(flags) == TS_SCHED_THM2 || sched_of(flags) == TS_SCHED_BITONIC))
+        return kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
     if (op != TS_OP_SORT || num_tiles <= 0 || total_len < 0) return kWorkspaceBytes;
     const int sched = resolve_sort_sched(flags, max_tile_len);
     if (sched == TS_SCHED_MERGE) return ts::merge_layout(num_tiles, total_len, max_tile_len).total;
@@ -159,6 +162,58 @@ ts_status ts_check(void* workspace, void* stream) {
     return fail(TS_ERR_INVALID, "device reported: %s", msg.c_str());
 }
 
+// Partition as the sorting of labels (the abstract's definition) with a 4096-key
+// sort schedule: Theorem 2 (THM2) or the bitonic network.  The composites carry the
+// position, so the order inside a class is the input order, as for the split
+// schedule.  The payload follows through the permutation like tile_sort's.
+ts_status partition_by_sort(const uint32_t* labels_in, uint32_t* labels_out,
+                            const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
+                            int64_t elem_stride, int64_t chan_stride, uint32_t num_classes,
+                            int32_t* perm_out, const int64_t* tile_offsets, int64_t num_tiles,
+                            int64_t max_tile_len, uint32_t flags, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+    const int sched = sched_of(flags);
+    if (max_tile_len > ts::sort_capacity(sched))
+        return fail(TS_ERR_UNSUPPORTED, "tile_partition: max_tile_len %lld > %lld for this schedule",
+                    (long long)max_tile_len, (long long)ts::sort_capacity(sched));
+    if (num_tiles == 0) return TS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (flags & TS_FLAG_VALIDATE) {
+        e = ts::launch_label_check(labels_in, tile_offsets, num_tiles, num_classes,
+                                   (uint32_t*)workspace, s);
+        if (e != hipSuccess) return hip_status(e, "tile_partition label check");
+    }
+    ts::SortArgs a{};
+    a.keys_in = labels_in;
+    a.keys_out = labels_out;
+    a.pay = ts::PayloadRef{payload_in, payload_out, channels, elem_stride, chan_stride};
+    a.perm_out = perm_out;
+    a.offsets = tile_offsets;
+    a.num_tiles = num_tiles;
+    a.err = (uint32_t*)workspace;
+    if (channels > 0 && a.perm_out == nullptr) {
+        const size_t need = kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
+        if (workspace_bytes < need)
+            return fail(TS_ERR_WORKSPACE, "tile_partition: payload without perm_out needs %zu workspace bytes", need);
+        a.perm_out = (int32_t*)((char*)workspace + kWorkspaceBytes);
+    }
+    e = ts::launch_sort(a, max_tile_len, sched, s);
+    if (e != hipSuccess) return hip_status(e, "tile_partition launch");
+    if (channels > 0) {
+        ts::PermuteArgs p{};
+        p.pay = a.pay;
+        p.pi = a.perm_out;
+        p.direction = TS_GATHER;
+        p.offsets = tile_offsets;
+        p.num_tiles = num_tiles;
+        p.err = a.err;
+        e = ts::launch_permute_split(p, 4096, s);
+        if (e != hipSuccess) return hip_status(e, "tile_partition payload gather launch");
+    }
+    return TS_OK;
+}
+
 ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
                          const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
                          int64_t elem_stride, int64_t chan_stride, uint32_t num_classes,
@@ -176,6 +231,11 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
     if (st != TS_OK) return st;
     if (channels > 1)
         return fail(TS_ERR_UNSUPPORTED, "tile_partition: channels > 1 not supported (got %u)", channels);
+    const int sched = sched_of(flags);
+    if (sched == TS_SCHED_THM2 || sched == TS_SCHED_BITONIC)
+        return partition_by_sort(labels_in, labels_out, payload_in, payload_out, channels, elem_stride,
+                                 chan_stride, num_classes, perm_out, tile_offsets, num_tiles,
+                                 max_tile_len, flags, workspace, workspace_bytes, stream);
     if (max_tile_len > ts::partition_split_capacity())
         return fail(TS_ERR_UNSUPPORTED, "tile_partition: max_tile_len %lld > %lld",
                     (long long)max_tile_len, (long long)ts::partition_split_capacity());
@@ -191,12 +251,17 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
     a.validate = (flags & TS_FLAG_VALIDATE) ? 1u : 0u;
     a.err = (uint32_t*)workspace;
     hipStream_t s = (hipStream_t)stream;
-    const int sched = sched_of(flags);
     hipError_t e;
     switch (sched) {
         case TS_SCHED_AUTO:
         case TS_SCHED_SPLIT: e = ts::launch_partition_split(a, max_tile_len, s); break;
-        case TS_SCHED_NAIVE: e = ts::launch_partition_naive(a, max_tile_len, s); break;
+        case TS_SCHED_NAIVE:
+            // the baseline kernel has no checks of its own
+            e = a.validate ? ts::launch_label_check(labels_in, tile_offsets, num_tiles, num_classes,
+                                                    a.err, s)
+                           : hipSuccess;
+            if (e == hipSuccess) e = ts::launch_partition_naive(a, max_tile_len, s);
+            break;
         default: return fail(TS_ERR_UNSUPPORTED, "tile_partition: schedule %d not available", sched);
     }
     return hip_status(e, "tile_partition launch");

@@ -60,11 +60,11 @@ struct SortArgs {
 
 // Sorting tiles of uneven length by pieces and merges (merge.hip).
 constexpr int MERGE_PIECE = 4096;          // keys per wavefront work item
-constexpr int MERGE_POS_BITS = 20;         // tile positions fit in 20 bits
+constexpr int MERGE_POS_BITS = 28;         // tile positions fit in 28 bits
 constexpr int64_t MERGE_MAX_TILE = int64_t(1) << MERGE_POS_BITS;
-constexpr int MERGE_MAX_ROUNDS = 8;        // log2(MERGE_MAX_TILE / MERGE_PIECE)
+constexpr int MERGE_MAX_ROUNDS = 16;       // log2(MERGE_MAX_TILE / MERGE_PIECE)
 constexpr int MERGE_COUNTER_WORD = 16;     // first counter word in the workspace header
-constexpr int MERGE_COUNTER_BYTES = 64;    // words 16 .. 31: 4 bins, pieces, rounds 0 .. 7
+constexpr int MERGE_COUNTER_BYTES = 96;    // words 16 .. 39: 4 bins, pieces, rounds 0 .. 15 at 8 + r
 
 // Byte offsets of the regions a merge-schedule sort carves out of the workspace.
 struct MergeLayout {
@@ -99,7 +99,9 @@ int num_cus();
 // Each returns hipSuccess or the launch error.  `cap` is the kernel's tile capacity.
 hipError_t launch_partition_split(const PartitionArgs& a, int64_t max_len, hipStream_t s);
 hipError_t launch_partition_naive(const PartitionArgs& a, int64_t max_len, hipStream_t s);
-hipError_t launch_partition_thm2(const PartitionArgs& a, int64_t max_len, hipStream_t s);
+// Flags labels >= num_classes (partition through the sort schedules).
+hipError_t launch_label_check(const uint32_t* labels, const int64_t* offsets, int64_t num_tiles,
+                              uint32_t num_classes, uint32_t* err, hipStream_t s);
 hipError_t launch_permute_split(const PermuteArgs& a, int64_t max_len, hipStream_t s);
 hipError_t launch_permute_naive(const PermuteArgs& a, int64_t max_len, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, int64_t max_len, int sched, hipStream_t s);

@@ -1,4 +1,4 @@
-// Sorting a batch of tiles of uneven length (1 .. 2^20 keys each) in a fixed sequence of
+// Sorting a batch of tiles of uneven length (1 .. 2^28 keys each) in a fixed sequence of
 // launches that a stream capture can record once and replay.
 //
 // The tile-local problem is the paper's sorting problem (Sec. 1, "Problems of
@@ -10,7 +10,7 @@
 // a time: a merge-path co-rank search picks the A and B ranges that produce them, A is
 // loaded ascending and B descending (a bitonic sequence) and 12 merge stages sort it.
 //
-// Items are 64-bit composites  slot << 52 | key << 20 | position,  distinct within a
+// Items are 64-bit composites  slot << 60 | key << 28 | position,  distinct within a
 // tile, so the result is the unique stable order.  `slot` packs up to eight tiles of at
 // most 512 keys (four of 1024, two of 2048) into one wavefront: each tile owns a slot of
 // 4096 / P positions and its padding sorts to the end of its slot.
@@ -36,7 +36,7 @@ using namespace bt;
 constexpr int K = MERGE_PIECE;
 constexpr int POS_BITS = MERGE_POS_BITS;
 constexpr uint64_t POS_MASK = (uint64_t(1) << POS_BITS) - 1;
-constexpr int SLOT_SHIFT = 52;
+constexpr int SLOT_SHIFT = 60;  // slot (3 bits) above key and position
 constexpr uint64_t PAD = ~uint64_t(0);
 
 int g_merge_pack = 1;
@@ -124,9 +124,11 @@ __global__ __launch_bounds__(256) void merge_bin_kernel(MergeArgs a) {
 // from the composites; the payload is gathered through the positions 16 registers at a
 // time, every load of a group issued before any is used (a load per register inside
 // its own branch would wait for each one in turn).
+// `narrow`: every payload offset of the tile (position x elem_stride x 4 bytes) fits
+// in 32 bits, so gathers use a wave-uniform base plus 32-bit offsets.
 template <int NC>
 TS_DEV void store_final_regs(const SortArgs& s, int64_t o, int64_t rb, int nvalid,
-                             const uint64_t (&v)[R], int c0, int lane) {
+                             const uint64_t (&v)[R], int c0, int lane, bool narrow) {
     const int ln = (int)opaque((uint32_t)lane);
     const PayloadRef& p = s.pay;
     // keys and positions, addressed as one wave-uniform pointer plus 32-bit byte
@@ -145,9 +147,6 @@ TS_DEV void store_final_regs(const SortArgs& s, int64_t o, int64_t rb, int nvali
         }
     }
     if (p.channels == 0) return;
-    // (positions are below 2^20, so with at most 1024 words per element every payload
-    // offset inside the tile fits in 32 bits)
-    const bool narrow = p.es <= 1024;
     constexpr int G = NC < 16 ? NC : 16;
 #pragma unroll 1
     for (uint32_t ch = 0; ch < p.channels; ++ch) {
@@ -178,6 +177,10 @@ TS_DEV void store_final_regs(const SortArgs& s, int64_t o, int64_t rb, int nvali
             }
         }
     }
+}
+
+TS_DEV bool narrow_payload(const MergeArgs& a) {
+    return (uint64_t)a.max_len * (uint64_t)a.s.pay.es * 4u <= (uint64_t(1) << 32);
 }
 
 // Tile of bin entry e (or none past the bin's count): offset and length, wave-uniform.
@@ -238,7 +241,7 @@ TS_DEV void store_packed(const uint64_t (&v)[R], const MergeArgs& a, int bin, ui
         int64_t o;
         int n;
         bin_tile(a, bin, cnt, item * P + sl, o, n);
-        store_final_regs<CPS>(a.s, o, 0, n, v, sl * CPS, lane);
+        store_final_regs<CPS>(a.s, o, 0, n, v, sl * CPS, lane, narrow_payload(a));
     }
 }
 
@@ -397,7 +400,7 @@ void merge_round_kernel(MergeArgs a, int r) {
         const int64_t ob = g.ps + g.d0;  // tile position of output rank 0
         const int nout = (int)(g.d1 - g.d0);
         if (LAST) {
-            store_final_regs<R>(a.s, g.o, ob, nout, v, 0, lane);
+            store_final_regs<R>(a.s, g.o, ob, nout, v, 0, lane, narrow_payload(a));
         } else {
             uint64_t* ob_ptr = out_run + g.o + ob;
 #pragma unroll

@@ -118,13 +118,14 @@ def tile_partition(labels: torch.Tensor, payload: Optional[torch.Tensor] = None,
         labels_out = torch.empty_like(labels)
     if want_perm and perm_out is None:
         perm_out = torch.empty(n, dtype=torch.int32, device=dev)
-    ws = workspace(dev)
     flags = _lib.sched_flags(schedule) | (_lib.TS_FLAG_VALIDATE if validate else 0)
     lib = _lib.load()
+    T = off.numel() - 1
+    ml = _max_len(off, max_tile_len)
+    ws = workspace(dev, lib.ts_workspace_bytes(_lib.TS_OP_PARTITION, flags, T, n, ml, ch))
     _lib.check(lib.tile_partition(_ptr(labels), _ptr(labels_out), _ptr(payload), _ptr(payload_out),
-                                  ch, es, cs, num_classes, _ptr(perm_out), _ptr(off),
-                                  off.numel() - 1, _max_len(off, max_tile_len), flags, _ptr(ws),
-                                  ws.numel() * 4, _stream(dev)))
+                                  ch, es, cs, num_classes, _ptr(perm_out), _ptr(off), T, ml, flags,
+                                  _ptr(ws), ws.numel() * 4, _stream(dev)))
     return labels_out, payload_out, perm_out
 
 

@@ -87,9 +87,9 @@ def test_sort_argument_validation(lib):
     # the bitonic schedule holds 4096 keys per tile
     rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 8192, 8192, 3 << 8, ws, 256, None)
     assert rc == 2
-    # the merge schedule holds 2^20 keys per tile
-    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 1 << 21, (1 << 20) + 1, merge,
-                       ws, 1 << 30, None)
+    # the merge schedule holds 2^28 keys per tile
+    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 1 << 29, (1 << 28) + 1, merge,
+                       ws, 1 << 40, None)
     assert rc == 2
     # the merge schedule needs its workspace
     rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 65536, 65536, merge, ws, 256, None)

@@ -6,7 +6,7 @@ from paper_1507_01391_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = ["split", "naive"]
+SCHEDULES = ["split", "naive", "thm2", "bitonic"]
 
 
 @pytest.fixture(scope="module")
@@ -48,7 +48,7 @@ def test_uneven_tiles_random_labels(ts, oracle, schedule, num_classes):
     run_and_compare(ts, oracle, labels, payload, off, num_classes, schedule, max_len=4096)
 
 
-@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("schedule", ["split", "naive"])
 @pytest.mark.parametrize("cap", [1024, 2048, 8192, 16384])
 def test_large_tiles(ts, oracle, schedule, cap):
     rng = np.random.default_rng(cap)
@@ -79,13 +79,14 @@ def test_no_payload_and_degenerate_labels(ts, oracle):
         run_and_compare(ts, oracle, labels, None, off, 64, "split")
 
 
-def test_validate_flags_bad_label(ts):
+@pytest.mark.parametrize("schedule", ["split", "thm2", "naive"])
+def test_validate_flags_bad_label(ts, schedule):
     import torch
     from tests.gpu_util import dev
     labels = np.zeros(4096, np.uint32)
     labels[77] = 64
     ts.tile_partition(dev(labels), None, dev(np.array([0, 4096], np.int64)), num_classes=64,
-                      validate=True)
+                      validate=True, schedule=schedule)
     with pytest.raises(RuntimeError, match="num_classes"):
         ts.check_device_errors()
     torch.cuda.synchronize()
@@ -98,3 +99,16 @@ def test_tile_longer_than_capacity_is_reported(ts):
     ts.tile_partition(dev(labels), None, dev(np.array([0, 8192], np.int64)), max_tile_len=4096)
     with pytest.raises(RuntimeError, match="capacity"):
         ts.check_device_errors()
+
+
+@pytest.mark.parametrize("schedule", ["thm2", "bitonic"])
+def test_sort_schedules_payload_without_perm(ts, oracle, schedule):
+    labels, payload, off = inputs.partition(seed=25, num_tiles=50, n=4096)
+    from tests.gpu_util import dev, host_u32
+    want_l, want_p, _ = oracle.tile_partition(labels, payload.view(np.uint32), off, num_classes=64,
+                                              nthreads=8)
+    lo, po, perm = ts.tile_partition(dev(labels), dev(payload), dev(off), 64, max_tile_len=4096,
+                                     schedule=schedule, want_perm=False)
+    ts.check_device_errors()
+    assert perm is None
+    assert np.array_equal(host_u32(lo), want_l) and np.array_equal(host_u32(po), want_p)

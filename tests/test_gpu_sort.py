@@ -190,3 +190,14 @@ def test_merge_graph_replay(ts, oracle):
         assert np.array_equal(pm.cpu().numpy(), wperm), rep
         assert np.array_equal(po.cpu().numpy().view(np.uint32), np.asarray(wp).view(np.uint32)), rep
     ts.check_device_errors()
+
+
+def test_merge_one_large_array(ts, oracle):
+    """One array of 2^24 keys sorted as a single tile (pieces plus 12 merge rounds)."""
+    rng = np.random.default_rng(43)
+    n = 1 << 24
+    keys = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    keys[::3] = rng.integers(0, 4096, size=keys[::3].shape[0], dtype=np.uint32)   # ties
+    payload = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    off = np.array([0, n], np.int64)
+    run_and_compare(ts, oracle, keys, payload, off, "merge", max_len=n)
