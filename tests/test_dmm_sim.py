@@ -169,3 +169,89 @@ def test_binary_split_lsd_is_a_stable_partition(sim):
         phys[dest] = order            # physical array after the split
         order = phys[sim.split_virtual_order(0, n, zeros)]
     assert np.array_equal(order, np.argsort(labels, kind="stable"))
+
+
+# ---- layout moves of the register sort (32-bit planes, measured gfx950 model) --------
+# 32-bit accesses: two 32-lane halves over 32 banks; the stricter 64-bank / 64-lane DMM
+# reading is checked too.
+B32_MODELS = [(32, 32), (64, 64)]
+
+
+def move_dst(move, L, c):
+    """Destination (lane, register) of register c of lane L for the three moves."""
+    if move == "T":
+        return c, L
+    if move == "RM2CM":       # 8-row super-row, row-major p = 64 i + c -> column-major
+        return (L & ~7) + (c & 7), 8 * (L & 7) + (c >> 3)
+    return (L & ~7) + (c >> 3), 8 * (c & 7) + (L & 7)   # CM2RM
+
+
+def move_skew(move, cd):
+    return cd if move == "T" else (cd >> 3 if move == "RM2CM" else cd & 7)
+
+
+def move_write_word(move, L, c):
+    Ld, cd = move_dst(move, L, c)
+    if move == "T":
+        return 65 * L + c            # the transpose uses a row pitch of 65 words
+    return cd * 64 + ((Ld + move_skew(move, cd)) & 63)
+
+
+def move_read_word(move, L, c):
+    if move == "T":
+        return 65 * c + L
+    return c * 64 + ((L + move_skew(move, c)) & 63)
+
+
+@pytest.mark.parametrize("move", ["T", "RM2CM", "CM2RM"])
+def test_layout_moves_are_the_intended_permutations(move):
+    # whatever register c of lane L writes is read back by lane Ld as register cd
+    written = {move_write_word(move, L, c): (L, c) for L in range(64) for c in range(64)}
+    assert len(written) == 4096                      # no two writes share a word
+    for L in range(64):
+        for c in range(64):
+            src = written[move_read_word(move, L, c)]
+            assert move_dst(move, *src) == (L, c)
+    if move != "T":
+        # the super-row moves are inverse to each other and stay inside super-rows
+        for L in range(64):
+            for c in range(64):
+                Ld, cd = move_dst(move, L, c)
+                assert Ld >> 3 == L >> 3
+                back = "CM2RM" if move == "RM2CM" else "RM2CM"
+                assert move_dst(back, Ld, cd) == (L, c)
+
+
+@pytest.mark.parametrize("move", ["T", "RM2CM", "CM2RM"])
+@pytest.mark.parametrize("banks,phase", B32_MODELS)
+def test_layout_moves_conflict_free(sim, move, banks, phase):
+    model = sim.BankModel(banks, phase, 1)
+    for c in range(64):   # one write and one read instruction per register
+        w = [(L, move_write_word(move, L, c)) for L in range(64)]
+        r = [(L, move_read_word(move, L, c)) for L in range(64)]
+        assert sim.step_conflicts(w, model, is_read=False) == 0
+        assert sim.step_conflicts(r, model, is_read=True) == 0
+
+
+def test_unskewed_transpose_would_conflict(sim):
+    # the same transpose with a row pitch of 64 puts a whole write on one bank
+    model = sim.BankModel(32, 32, 1)
+    w = [(L, 64 * L + 5) for L in range(64)]
+    assert sim.step_conflicts(w, model, is_read=False) == 2 * 31
+
+
+@pytest.mark.parametrize("m", [64, 128, 256])
+def test_router_placement_conflict_free(sim, m):
+    """Placement of the bank router: group g (m slots) holds the items bound for bank g.
+    Step t: lane l reads slot l*m + ((t + l) mod m) (64-bit reads, 32-lane phases over 64
+    banks) and writes it to its destination, a slot congruent to l modulo 64 (64-bit
+    writes, 16-lane phases)."""
+    rd = sim.BankModel(64, 32, 2)
+    wr = sim.BankModel(64, 16, 2)
+    rng = np.random.default_rng(m)
+    for t in range(m):
+        reads = [(l, 2 * (l * m + ((t + l) % m))) for l in range(64)]
+        assert sim.step_conflicts(reads, rd, is_read=True) == 0
+        slots = [64 * int(rng.integers(0, m)) + l for l in range(64)]
+        writes = [(l, 2 * s) for l, s in enumerate(slots)]
+        assert sim.step_conflicts(writes, wr, is_read=False) == 0
