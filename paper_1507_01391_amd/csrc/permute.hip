@@ -10,6 +10,8 @@
 // bits of the high word, source in the high 16), so either direction can also write
 // the inverse permutation at no extra routing: a scatter's caller can then undo it
 // with another scatter instead of a two-routing gather.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "route.hpp"
@@ -18,13 +20,16 @@ namespace ts {
 
 namespace {
 
-template <int NW, int CAP, bool GATHER, int WPE>
+// REPLAY (for two or more payload channels): channel 0 is routed and recorded, the
+// other channels replay the record two per 64-bit item.
+template <int NW, int CAP, bool GATHER, int WPE, bool REPLAY>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
     using R = Router<NW, CAP>;
     constexpr int CPW = R::CPW;
     __shared__ uint64_t A[CAP];
     __shared__ int wz[NW];
+    __shared__ typename std::conditional<REPLAY, typename R::Plan, int>::type plan;
     const int lane0 = lane_id();
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr bool gather = GATHER;
@@ -80,8 +85,11 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
             for (int j = 0; j < CPW; ++j) dst[j] |= (uint32_t)(64 * (w * CPW + j) + lane) << 16;
         }
 
-        // a scatter asked only for the inverse still routes once (with no payload)
-        const uint32_t nroute = (!gather && a.inv_out && a.pay.channels == 0) ? 1u : a.pay.channels;
+        // a scatter asked only for the inverse still routes once (with no payload);
+        // with REPLAY only channel 0 is routed here
+        const uint32_t nroute = REPLAY ? 1u
+                                       : ((!gather && a.inv_out && a.pay.channels == 0) ? 1u : a.pay.channels);
+        uint32_t pdst[REPLAY ? CPW : 1];
 #pragma unroll 1
         for (uint32_t c = 0; c < nroute; ++c) {
             // per-column addresses are recomputed per channel instead of being kept
@@ -95,7 +103,8 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
                               lc, xv, offs);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) e[j] = pack(dst[j], xv[j]);
-            R::route(A, wz, e, w, lane);
+            if constexpr (REPLAY) R::template route<true>(A, wz, e, w, lane, &plan, pdst);
+            else R::route(A, wz, e, w, lane);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
                 const int v = 64 * (w * CPW + j) + lc;
@@ -109,13 +118,43 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
             }
             __syncthreads();  // A is reused by the next channel / tile
         }
+        if constexpr (REPLAY) {
+#pragma unroll 1
+            for (uint32_t c = 1; c < a.pay.channels; c += 2) {
+                const int lc = (int)opaque((uint32_t)lane);
+                const uint32_t own_c = (uint32_t)lc * 8u + (uint32_t)(w * CPW * 512);
+                const bool two = c + 1 < a.pay.channels;
+                const int64_t cb0 = (int64_t)c * a.pay.cs;
+                const int64_t cb1 = two ? cb0 + a.pay.cs : cb0;
+                uint32_t x0[CPW], x1[CPW];
+                load_columns<CPW>(a.pay.in + cb0, a.pay.es, o, n, w * CPW, lc, x0, offs);
+                load_columns<CPW>(a.pay.in + cb1, a.pay.es, o, n, w * CPW, lc, x1, offs);
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) e[j] = pack(x1[j], x0[j]);
+                R::replay(A, &plan, e, pdst, w, lane);
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) {
+                    const int v = 64 * (w * CPW + j) + lc;
+                    const uint64_t x = lds_load_u64_whole(A, own_c + 512u * j);
+                    if (v < n) {
+                        store_item(a.pay.out + cb0, a.pay.es, o, v, lo32(x));
+                        if (two) store_item(a.pay.out + cb1, a.pay.es, o, v, hi32(x));
+                    }
+                }
+                __syncthreads();  // A is reused by the next pair / tile
+            }
+        }
     }
 }
 
 template <int NW, int CAP, int WPE = 0>
 hipError_t launch_perm(const PermuteArgs& a, hipStream_t s) {
-    auto kern = (a.direction == 1) ? permute_split_kernel<NW, CAP, true, WPE>
-                                   : permute_split_kernel<NW, CAP, false, WPE>;
+    const bool replay = a.pay.channels >= 2;
+    auto kern = (a.direction == 1)
+                    ? (replay ? permute_split_kernel<NW, CAP, true, WPE, true>
+                              : permute_split_kernel<NW, CAP, true, WPE, false>)
+                    : (replay ? permute_split_kernel<NW, CAP, false, WPE, true>
+                              : permute_split_kernel<NW, CAP, false, WPE, false>);
     const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, a.offsets);
     return hipGetLastError();

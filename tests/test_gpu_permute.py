@@ -127,3 +127,29 @@ def test_scatter_by_inverse_equals_gather(ts):
     g1 = ts.tile_permute(dev(x), dev(pi), "gather", dev(off))
     g2 = ts.tile_permute(dev(x), inv, "scatter", dev(off))
     assert np.array_equal(host_u32(g1), host_u32(g2))
+
+
+@pytest.mark.parametrize("channels", [2, 5, 8])
+@pytest.mark.parametrize("direction", ["scatter", "gather"])
+@pytest.mark.parametrize("cap", [4096, 8192, 16384])
+def test_multichannel_replay(ts, oracle, channels, direction, cap):
+    """Channel 0 is routed and recorded, the others replay the record two at a time."""
+    rng = np.random.default_rng(cap + channels)
+    sizes = np.array([cap, cap - 1, 1, 0, cap // 2 + 5, cap])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pi = np.concatenate([rng.permutation(int(s)) for s in sizes]).astype(np.int32)
+    x = rng.integers(0, 2**32, size=(channels, off[-1]), dtype=np.uint32)
+    run_and_compare(ts, oracle, x, pi, off, direction, max_len=cap)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_multichannel_replay_variants(ts, oracle, variant):
+    x, pi, _, off = inputs.permutation(seed=72, num_tiles=12, n=8192, family="transpose")
+    x4 = np.stack([x, -x, 2 * x, x + 1]).astype(np.float32)
+    prev = ts.knob("permute_variant", 0)
+    ts.tune("permute_variant", variant)
+    try:
+        for direction in ("scatter", "gather"):
+            run_and_compare(ts, oracle, x4, pi, off, direction, max_len=8192)
+    finally:
+        ts.tune("permute_variant", prev)
