@@ -204,4 +204,32 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+namespace {
+
+// One workgroup per tile (grid-stride over tiles), threads stride over the tile.
+__global__ __launch_bounds__(256) void label_check_kernel(const uint32_t* __restrict__ labels,
+                                                          const int64_t* __restrict__ offs,
+                                                          int64_t num_tiles, uint32_t num_classes,
+                                                          uint32_t* err) {
+    for (int64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
+        const int64_t o = offs[t];
+        const int64_t n = offs[t + 1] - o;
+        bool bad = false;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) bad |= labels[o + i] >= num_classes;
+        flag_error(err, bad, ERR_BAD_LABEL);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_label_check(const uint32_t* labels, const int64_t* offsets, int64_t num_tiles,
+                              uint32_t num_classes, uint32_t* err, hipStream_t s) {
+    if (num_tiles == 0) return hipSuccess;
+    const int64_t g = num_tiles < 8192 ? num_tiles : 8192;
+    hipLaunchKernelGGL(label_check_kernel, dim3((unsigned)g), dim3(256), 0, s, labels, offsets,
+                       num_tiles, num_classes, err);
+    return hipGetLastError();
+}
+
+
 }  // namespace ts

@@ -7,6 +7,7 @@ in a fixed order, so counter rows map to patterns by dispatch order (PROBE_PATTE
 
     python -m paper_1507_01391_amd.profile_run partition --schedule split --tiles 16384
     python -m paper_1507_01391_amd.profile_run permute --schedule split --direction gather
+    python -m paper_1507_01391_amd.profile_run permute --n 16384 --tiles 1024 --channels 8
     python -m paper_1507_01391_amd.profile_run sort --schedule bitonic --tiles 16384
     python -m paper_1507_01391_amd.profile_run segments --segments 20000
     python -m paper_1507_01391_amd.profile_run copy --bytes 1073741824
@@ -86,6 +87,8 @@ def run_partition(a):
 
 def run_permute(a):
     x, pi, _, off = inputs.permutation(num_tiles=a.tiles, n=a.n, family=a.family)
+    if a.channels > 1:   # channel-planar payload: x, -x, 2x, ...
+        x = np.stack([x * (1 + c // 2) * (-1) ** c for c in range(a.channels)]).astype(np.float32)
     dx, dpi, do = _dev(x), _dev(pi), _dev(off)
     y = torch.empty_like(dx)
     _repeat(lambda: ops.tile_permute(dx, dpi, a.direction, do, max_tile_len=a.n, out=y,
@@ -137,6 +140,7 @@ def main(argv=None):
     p.add_argument("--family", default="uniform")
     p.add_argument("--tiles", type=int, default=4096)
     p.add_argument("--n", type=int, default=8192)
+    p.add_argument("--channels", type=int, default=1)
     p = sub.add_parser("sort")
     p.add_argument("--schedule", default="bitonic")
     p.add_argument("--tiles", type=int, default=16384)
