@@ -181,8 +181,10 @@ const char* ts_version(void);
  * Measurement helpers (not part of the hot path).
  * ------------------------------------------------------------------------------ */
 
-/* Plain device-to-device copy of `bytes` bytes with 16-byte vector loads/stores:
-   the HBM bandwidth reference kernel. */
+/* Plain device-to-device copy of `bytes` bytes (src, dst: device, 16-byte aligned,
+   not overlapping) with streaming 16-byte vector loads and stores, one contiguous
+   32 KiB chunk per workgroup: the HBM bandwidth reference kernel.  TS_ERR_INVALID for
+   NULL or misaligned pointers. */
 ts_status ts_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 /*
@@ -199,16 +201,26 @@ ts_status ts_lds_probe(const uint32_t* lane_words, int op, int width, int iters,
                        int groups, uint64_t* cycles_out, uint32_t* sink, void* stream);
 
 /* Override a tuning knob of the kernel-selection table (used by the autotuner).
-   Knobs: "partition_waves_4096" (1, 2, 4, 8 or 16 waves per workgroup; 104 and 108:
-   4 or 8 waves with registers capped so four workgroups fit on a CU; 110: 8 waves,
-   five workgroups per CU; 106 / 116: 8 waves, three workgroups per CU, with / without
-   loading the next tile during the current one; 118: 8 waves without prefetching the
-   next tile; 204, 208, 216: two tiles per workgroup with 4, 8 or 16 waves); "permute_variant" (0: registers as
-   the compiler chooses; 1: registers capped for more workgroups per CU; 2: 8-wave
-   workgroups for 8192-item tiles); "merge_pack" (1: tiles of up to 2048 keys share a
-   wavefront in the merge schedule, 0: one tile per wavefront); "sort_plan_4096",
-   "sort_plan_8192", "sort_plan_16384" (the TS_SCHED_* value that tile_sort's AUTO
-   uses for max_tile_len up to that length).
+   Knobs:
+   "partition_waves_4096" -- split partition kernel for tiles of up to 4096 items:
+      1, 2, 4, 8 or 16 waves per workgroup on a persistent grid; 104 / 108: 4 / 8
+      waves with registers capped so four workgroups fit on a CU; 106: 8 waves, three
+      workgroups per CU, loading the next tile during the current one; 164 / 166 / 168:
+      4 / 8 / 8 waves, one workgroup per tile with streaming global accesses, registers
+      capped for 4 / 3 / 4 workgroups per CU (168 is the default); 176: as 166 with
+      plain accesses.
+   "permute_variant" -- router permute kernel for tiles of 4097..8192 items: 0: 16
+      waves, persistent grid; 1: the same with registers capped for two workgroups per
+      CU; 2: 8 waves; 6 (default) / 7: 16 capped waves, one workgroup per tile, with /
+      without streaming accesses; 8: 6 on a persistent grid.
+   "oneshot" -- launch shape of every other split-partition, split-sort and permute
+      kernel: 1 (default) one workgroup per tile with streaming accesses, 0 a
+      persistent grid.
+   "naive_oneshot" -- the same choice for the naive-LDS kernels (default 0).
+   "merge_pack" -- 1: tiles of up to 2048 keys share a wavefront in the merge
+      schedule, 0: one tile per wavefront.
+   "sort_plan_4096", "sort_plan_8192", "sort_plan_16384" -- the TS_SCHED_* value that
+      tile_sort's AUTO uses for max_tile_len up to that length.
    Returns TS_ERR_INVALID for an unknown knob or value. */
 ts_status ts_tune(const char* knob, int value);
 

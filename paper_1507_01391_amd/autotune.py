@@ -32,8 +32,9 @@ KNOBS = {
     "sort_plan_8192": ([SORT["merge"], SORT["split"]], SORT["merge"]),
     "sort_plan_16384": ([SORT["merge"], SORT["split"]], SORT["merge"]),
     "merge_pack": ([1, 0], 1),
-    "partition_waves_4096": ([106, 116, 108, 110, 8, 104], 106),
-    "permute_variant": ([0, 1, 2], 0),
+    "oneshot": ([1, 0], 1),
+    "partition_waves_4096": ([168, 176, 166, 164, 106, 108, 104], 168),
+    "permute_variant": ([6, 7, 8, 1, 0, 2], 6),
 }
 
 
@@ -135,6 +136,24 @@ def tune(quick: bool = False, log=print) -> dict:
     # packing of short tiles in the merge schedule
     run, n = _sort_bench(rng, 256, 4096, total, lambda v: "merge")
     choose("merge_pack", run, n, set_knob=True)
+
+    # launch shape of the kernels without a variant table: a partition of 2048-item
+    # tiles plus a permutation of 4096-item tiles
+    tiles = total // 2048
+    lab2 = rng.permuted(np.tile(np.repeat(np.arange(64, dtype=np.int32), 32), (tiles, 1)), axis=1)
+    d_lab2 = torch.from_numpy(lab2.reshape(-1)).cuda()
+    d_pay2 = torch.randn(d_lab2.shape[0], device="cuda")
+    d_off2 = torch.arange(tiles + 1, device="cuda", dtype=torch.int64) * 2048
+    pi4 = np.argsort(rng.random((total // 4096, 4096)), axis=1).astype(np.int32).reshape(-1)
+    d_pi4 = torch.from_numpy(pi4).cuda()
+    d_off4 = torch.arange(total // 4096 + 1, device="cuda", dtype=torch.int64) * 4096
+    lo2, po2, y4 = torch.empty_like(d_lab2), torch.empty_like(d_pay2), torch.empty_like(d_pay2)
+
+    def shaped():
+        ops.tile_partition(d_lab2, d_pay2, d_off2, 64, max_tile_len=2048, labels_out=lo2, payload_out=po2)
+        ops.tile_permute(d_pay2, d_pi4, "scatter", d_off4, max_tile_len=4096, out=y4)
+    choose("oneshot", lambda v: shaped, 2 * total, set_knob=True)
+    del d_lab2, d_pay2, d_off2, d_pi4, d_off4, lo2, po2, y4
 
     # partition: 4096-item tiles, 64 classes with 64 copies each
     tiles = total // 4096

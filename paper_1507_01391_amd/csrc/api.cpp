@@ -383,16 +383,27 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
 ts_status ts_tune(const char* knob, int value) {
     if (knob == nullptr) return fail(TS_ERR_INVALID, "ts_tune: knob is NULL");
     if (std::strcmp(knob, "partition_waves_4096") == 0) {
-        static const int ok[] = {1, 2, 4, 8, 16, 104, 106, 108, 110, 116, 118, 204, 208, 216};
+        static const int ok[] = {1, 2, 4, 8, 16, 104, 106, 108, 164, 166, 168, 176};
         bool found = false;
         for (int v : ok) found |= (v == value);
         if (!found)
-            return fail(TS_ERR_INVALID, "ts_tune: partition_waves_4096 must be one of 1, 2, 4, 8, 16, 104, 106, 108, 110, 116, 118, 204, 208, 216");
+            return fail(TS_ERR_INVALID, "ts_tune: partition_waves_4096 must be one of 1, 2, 4, 8, 16, 104, 106, 108, 164, 166, 168, 176");
         ts::set_partition_waves(value);
         return TS_OK;
     }
+    if (std::strcmp(knob, "oneshot") == 0) {
+        if (value < 0 || value > 1) return fail(TS_ERR_INVALID, "ts_tune: oneshot must be 0 or 1");
+        ts::set_oneshot(value);
+        return TS_OK;
+    }
+    if (std::strcmp(knob, "naive_oneshot") == 0) {
+        if (value < 0 || value > 1) return fail(TS_ERR_INVALID, "ts_tune: naive_oneshot must be 0 or 1");
+        ts::set_naive_oneshot(value);
+        return TS_OK;
+    }
     if (std::strcmp(knob, "permute_variant") == 0) {
-        if (value < 0 || value > 2) return fail(TS_ERR_INVALID, "ts_tune: permute_variant must be 0, 1 or 2");
+        if (!(value == 0 || value == 1 || value == 2 || value == 6 || value == 7 || value == 8))
+            return fail(TS_ERR_INVALID, "ts_tune: permute_variant must be one of 0, 1, 2, 6, 7, 8");
         ts::set_permute_variant(value);
         return TS_OK;
     }
@@ -416,6 +427,8 @@ ts_status ts_tune(const char* knob, int value) {
 ts_status ts_copy(const void* src, void* dst, size_t bytes, void* stream) {
     if (bytes == 0) return TS_OK;
     if (src == nullptr || dst == nullptr) return fail(TS_ERR_INVALID, "ts_copy: NULL pointer");
+    if (((uintptr_t)src | (uintptr_t)dst) & 15u)
+        return fail(TS_ERR_INVALID, "ts_copy: src and dst must be 16-byte aligned");
     return hip_status(ts::launch_copy(src, dst, bytes, (hipStream_t)stream), "ts_copy launch");
 }
 

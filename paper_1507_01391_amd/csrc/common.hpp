@@ -58,13 +58,34 @@ TS_DEV uint32_t select_by_mask(uint64_t mask, uint32_t if0, uint32_t if1) {
     return r;
 }
 
+// Lane bit of `mask` set -> 0, else if0 (one v_cndmask with an inline-constant operand).
+TS_DEV uint32_t zero_if_mask(uint64_t mask, uint32_t if0) {
+    uint32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, 0, %2" : "=v"(r) : "v"(if0), "s"(mask));
+    return r;
+}
+
+// Sum of v over lanes 0 .. L-1 (L a power of two, at most 16), valid in lane L-1:
+// an inclusive prefix sum inside the first DPP row.
+template <int L, int S = 1>
+TS_DEV uint32_t row_prefix_sum(uint32_t v) {
+    static_assert(L >= 1 && L <= 16 && (L & (L - 1)) == 0, "one DPP row, power of two");
+    if constexpr (S < L) {
+        v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 | S, 0xF, 0xF, true);  // row_shr:S
+        return row_prefix_sum<L, 2 * S>(v);
+    } else {
+        return v;
+    }
+}
+
 // Issue CPW coalesced 32-bit global loads of one tile, column j = items 64*(c0+j) + lane,
 // with no waits between them and no branches around them.  Element g of the tile is at
 // base[(o + g) * stride].  Lanes past the end (and every lane when n <= 0) read from
 // `fallback` -- any always-readable address -- and the caller ignores those values.
 // Unit stride uses a wave-uniform tile pointer and 32-bit byte offsets (scalar-base
 // addressing); other strides use 64-bit addresses.
-template <int CPW, typename T>
+// NT: streaming (nontemporal) loads, for data read exactly once.
+template <int CPW, bool NT = false, typename T>
 TS_DEV void load_columns(const T* __restrict__ base, int64_t stride, int64_t o, int n, int c0,
                          int lane, T (&out)[CPW], const void* fallback) {
     const bool any = n > 0;
@@ -74,23 +95,26 @@ TS_DEV void load_columns(const T* __restrict__ base, int64_t stride, int64_t o, 
         for (int j = 0; j < CPW; ++j) {
             const uint32_t i = (uint32_t)(64 * (c0 + j) + lane);
             const uint32_t off = (i < (uint32_t)n) ? i * (uint32_t)sizeof(T) : 0u;
-            out[j] = *(const T*)(tb + off);
+            const T* p = (const T*)(tb + off);
+            out[j] = NT ? __builtin_nontemporal_load(p) : *p;
         }
     } else {
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
             const int i = 64 * (c0 + j) + lane;
             const T* p = (i < n) ? base + (o + i) * stride : (const T*)fallback;
-            out[j] = *p;
+            out[j] = NT ? __builtin_nontemporal_load(p) : *p;
         }
     }
 }
 
-// Store element g = 64*c + lane of a tile (g < n) at base[(o + g) * stride].
-template <typename T>
+// Store element g = 64*c + lane of a tile (g < n) at base[(o + g) * stride]; NT: a
+// streaming (nontemporal) store.
+template <bool NT = false, typename T>
 TS_DEV void store_item(T* __restrict__ base, int64_t stride, int64_t o, int g, T v) {
-    if (stride == 1) *(T*)((char*)(base + o) + (uint32_t)g * (uint32_t)sizeof(T)) = v;
-    else base[(o + g) * stride] = v;
+    T* p = (stride == 1) ? (T*)((char*)(base + o) + (uint32_t)g * (uint32_t)sizeof(T)) : base + (o + g) * stride;
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 // LDS accesses at a byte offset from the start of an LDS array.

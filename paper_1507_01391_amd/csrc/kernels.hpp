@@ -121,5 +121,8 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // Grid size for a persistent kernel: min(work items, resident blocks on the device).
 int persistent_grid(const void* kernel, int block_threads, size_t dyn_lds, int64_t work);
+void set_naive_oneshot(int v);
+void set_oneshot(int v);
+bool tile_oneshot();
 
 }  // namespace ts

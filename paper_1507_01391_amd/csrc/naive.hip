@@ -2,12 +2,25 @@
 // scatter to each item's computed destination.  The destinations of one wave
 // instruction are data dependent, so several lanes often hit one bank (bank
 // conflicts).  They exist only to be measured beside the conflict-free kernels.
+#include <algorithm>
+#include <cstdint>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace ts {
 
 namespace {
+
+// Launch shape of the naive kernels (tuning knob): a persistent grid, or one
+// workgroup per tile.
+static int g_naive_oneshot = 0;
+
+int naive_grid(const void* kern, int threads, int64_t tiles) {
+    return g_naive_oneshot ? (int)std::min<int64_t>(tiles, INT32_MAX)
+                           : persistent_grid(kern, threads, 0, tiles);
+}
+
 
 // Inclusive prefix sum across the 64 lanes of a wave.
 TS_DEV int wave_inclusive_scan(int v) {
@@ -127,7 +140,7 @@ __global__ __launch_bounds__(NW * 64) void partition_naive_kernel(PartitionArgs 
 template <int NW, int CAP>
 hipError_t launch_pn(const PartitionArgs& a, hipStream_t s) {
     auto kern = partition_naive_kernel<NW, CAP>;
-    const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
+    const int grid = naive_grid((const void*)kern, NW * 64, a.num_tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a);
     return hipGetLastError();
 }
@@ -188,7 +201,7 @@ __global__ __launch_bounds__(NW * 64) void permute_naive_kernel(PermuteArgs a) {
 template <int NW, int CAP>
 hipError_t launch_pmn(const PermuteArgs& a, hipStream_t s) {
     auto kern = permute_naive_kernel<NW, CAP>;
-    const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
+    const int grid = naive_grid((const void*)kern, NW * 64, a.num_tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a);
     return hipGetLastError();
 }
@@ -282,7 +295,7 @@ __global__ __launch_bounds__(NW * 64) void sort_naive_kernel(SortArgs a) {
 template <int NW, int CAP>
 hipError_t launch_sn(const SortArgs& a, hipStream_t s) {
     auto kern = sort_naive_kernel<NW, CAP>;
-    const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
+    const int grid = naive_grid((const void*)kern, NW * 64, a.num_tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a);
     return hipGetLastError();
 }
@@ -304,6 +317,8 @@ hipError_t launch_permute_naive(const PermuteArgs& a, int64_t max_len, hipStream
     if (max_len <= 8192) return launch_pmn<8, 8192>(a, s);
     return launch_pmn<16, 16384>(a, s);
 }
+
+void set_naive_oneshot(int v) { g_naive_oneshot = v; }
 
 hipError_t launch_partition_naive(const PartitionArgs& a, int64_t max_len, hipStream_t s) {
     if (a.num_tiles == 0) return hipSuccess;

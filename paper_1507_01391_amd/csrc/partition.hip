@@ -25,6 +25,9 @@
 // between passes; LDS holds one copy of the tile (8 bytes per item).  The next
 // tile's labels and payload are loaded into registers while the current tile is
 // being split, so HBM latency overlaps the LDS work.
+#include <algorithm>
+#include <cstdint>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -61,7 +64,7 @@ struct TileLoad {
 
 // Issue the global loads of one tile (no waits).  Lanes past the end read item 0 of
 // the tile (always valid when n > 0) and are replaced by padding later.
-template <int CPW, int CAP>
+template <int CPW, int CAP, bool NT = false>
 TS_DEV void issue_tile_load(const SplitArgs& a, const int64_t* __restrict__ offs, int64_t t,
                             int w, int lane, TileLoad<CPW>& L) {
     // Branch-free: an absent tile reads the offsets of tile 0 and loads nothing useful,
@@ -73,14 +76,15 @@ TS_DEV void issue_tile_load(const SplitArgs& a, const int64_t* __restrict__ offs
     L.o = o;
     L.n = !exists ? -1 : ((len > CAP) ? -2 : (int)len);
     const int nn = (L.n > 0) ? L.n : 0;
-    load_columns<CPW>(a.keys_in, 1, o, nn, w * CPW, lane, L.lab, offs);
-    load_columns<CPW>(a.pay_in, a.pay_es, o, a.has_pay ? nn : 0, w * CPW, lane, L.pay, offs);
+    load_columns<CPW, NT>(a.keys_in, 1, o, nn, w * CPW, lane, L.lab, offs);
+    load_columns<CPW, NT>(a.pay_in, a.pay_es, o, a.has_pay ? nn : 0, w * CPW, lane, L.pay, offs);
 }
 
-template <int NW, int CAP, int WPE, int MODE, int PF = -1>
+template <int NW, int CAP, int WPE, int MODE, int PF = -1, int NTM = 0>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
     constexpr int CPW = CAP / 64 / NW;  // columns per wave
+    constexpr bool NTL = (NTM & 1) != 0, NTS = (NTM & 2) != 0;  // streaming loads / stores
     // Whether the next tile's loads are issued before this tile is split (PF = 1 / 0).
     // By default narrow, uncapped waves prefetch and the rest load each tile when they
     // start it (WPE < 0: never prefetch).
@@ -94,7 +98,7 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
 
     TileLoad<CPW> L;
     int64_t t = blockIdx.x;
-    issue_tile_load<CPW, CAP>(a, offs, t, w, lane0, L);
+    issue_tile_load<CPW, CAP, NTL>(a, offs, t, w, lane0, L);
 
     for (; t < a.num_tiles; t += gridDim.x) {
         // lane-derived values (positions, addresses) are recomputed per tile rather
@@ -104,7 +108,7 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
         const int n = L.n;
         if (n == -2) {  // longer than this kernel's capacity: skip and flag
             if (threadIdx.x == 0) atomicOr(a.err, ERR_TILE_TOO_LONG);
-            issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
+            issue_tile_load<CPW, CAP, NTL>(a, offs, t + gridDim.x, w, lane, L);
             continue;
         }
         // The tile is padded to the kernel capacity: every wave always owns CPW full
@@ -134,7 +138,7 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
         if (a.validate) flag_error(a.err, bad, ERR_BAD_LABEL);
 
         // ---- prefetch the next tile while this one is split in LDS
-        if (PREFETCH) issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
+        if (PREFETCH) issue_tile_load<CPW, CAP, NTL>(a, offs, t + gridDim.x, w, lane, L);
 
         // ---- one stable split per label bit.  Addresses are byte offsets into A built from
         //      one lane-dependent register plus wave-uniform scalars and the DS immediate
@@ -143,41 +147,41 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
         const uint32_t neg_lane8 = 0u - lane8;
         const uint32_t fwd_base = lane8 + (uint32_t)(w * CPW * 512);  // column j at + 512 j
         for (int b = 0; b < a.nbits; ++b) {
-            // Zeros before this wave's first column (zb) and in the whole tile (zt).
-            constexpr bool KEEP = (NW > 1);  // ballots are kept between the two loops
-            uint64_t bal[KEEP ? CPW : 1];
+            // Zero masks of this wave's columns; zeros before this wave's first column (zb)
+            // and in the whole tile (zt).
+            constexpr bool KEEP = (NW > 1);  // masks are kept between the two loops
+            uint64_t zm[KEEP ? CPW : 1];
             int zb = 0, zt = 0;
             if (KEEP) {
                 int zc = 0;
 #pragma unroll
                 for (int j = 0; j < CPW; ++j) {
-                    bal[j] = ballot((hi32(e[j]) >> b) & 1u);
-                    zc += 64 - popc64(bal[j]);
+                    zm[j] = ballot(((hi32(e[j]) >> b) & 1u) == 0u);
+                    zc += popc64(zm[j]);
                 }
                 if (lane == 0) wz[w] = zc;
                 __syncthreads();  // every wave has read the previous pass and posted its count
-                const int mine = (lane < NW) ? wz[lane] : 0;
-#pragma unroll
-                for (int q = 0; q < NW; ++q) {
-                    const int v = __builtin_amdgcn_readlane(mine, q);
-                    zt += v;
-                    zb += (q < w) ? v : 0;
-                }
+                // lane q < NW holds wave q's count in the low half and, when q < w, again in
+                // the high half; one prefix sum over the first NW lanes yields zt and zb
+                const uint32_t mine = (lane < NW) ? (uint32_t)wz[lane] : 0u;
+                const uint32_t both = row_prefix_sum<NW>(mine | ((lane < w) ? mine << 16 : 0u));
+                const uint32_t s = (uint32_t)__builtin_amdgcn_readlane((int)both, NW - 1);
+                zt = (int)(s & 0xFFFFu);
+                zb = (int)(s >> 16);
             }
             if (NW == 1) wave_lds_fence();  // the previous pass's reads stay before these writes
-            // Write: zeros of column k go to z + rank0, ones to N-1-(ones before)-rank1.
+            // Write: a zero of column k goes to z + r0 and a one to N-1-(64k-z)-(lane-r0),
+            // with z the zeros before the column and r0 the zeros in lower lanes; i.e. to
+            // z + r0 + (one ? N-1-64k-lane : 0), the bracket folded into the rank count.
             int z = zb;  // zeros before the current column (whole tile, in order)
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
                 const int k = w * CPW + j;
-                const uint64_t bj = KEEP ? bal[KEEP ? j : 0] : ballot((hi32(e[j]) >> b) & 1u);
-                const uint32_t r0 = count_below(~bj);  // zeros in lower lanes
-                const uint32_t z8 = (uint32_t)__builtin_amdgcn_readfirstlane(z * 8);
-                const uint32_t o8 = (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 - 64 * k + z) * 8);
-                const uint32_t a0 = r0 * 8u + z8;                 // zero: z + rank0
-                const uint32_t a1 = (r0 * 8u + neg_lane8) + o8;   // one: N-1-(64k-z)-(lane-rank0)
-                lds_store(A, select_by_mask(bj, a0, a1), e[j]);
-                z += 64 - popc64(bj);
+                const uint64_t zj = KEEP ? zm[KEEP ? j : 0] : ballot(((hi32(e[j]) >> b) & 1u) == 0u);
+                const uint32_t one_off = zero_if_mask(zj, (uint32_t)(N - 1 - 64 * k) - (uint32_t)lane);
+                const uint32_t pos = count_below_plus(zj, one_off) + (uint32_t)z;
+                lds_store(A, pos * 8u, e[j]);
+                z += popc64(zj);
             }
             if (NW == 1) zt = z;
             if (NW > 1) __syncthreads();  // the split tile is complete
@@ -186,17 +190,20 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
             const uint32_t rev_base =
                 (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 + zt - 64 * w * CPW - 64 * (CPW - 1)) * 8) +
                 neg_lane8;  // column j (reversed) at + 512 (CPW-1-j)
+            // The turning point zt falls inside at most one wave's columns: the others take
+            // one uniform branch for all of theirs.
+            const int first = 64 * w * CPW;
+            if (first + 64 * CPW <= zt) {
 #pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-                const int base = 64 * (w * CPW + j);
-                if (base + 64 <= zt) {
-                    e[j] = lds_load(A, fwd_base + 512u * j);
-                } else if (base >= zt) {
-                    e[j] = lds_load(A, rev_base + 512u * (CPW - 1 - j));
-                } else {
-                    e[j] = lds_load(A, (lane < zt - base) ? fwd_base + 512u * j
-                                                          : rev_base + 512u * (CPW - 1 - j));
-                }
+                for (int j = 0; j < CPW; ++j) e[j] = lds_load(A, fwd_base + 512u * j);
+            } else if (first >= zt) {
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) e[j] = lds_load(A, rev_base + 512u * (CPW - 1 - j));
+            } else {
+#pragma unroll
+                for (int j = 0; j < CPW; ++j)
+                    e[j] = lds_load(A, (lane < zt - first - 64 * j) ? fwd_base + 512u * j
+                                                                   : rev_base + 512u * (CPW - 1 - j));
             }
         }
 
@@ -207,192 +214,51 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
             if (v < n) {
                 const uint32_t h = hi32(e[j]);
                 if (MODE == 0) {
-                    if (a.keys_out) store_item(a.keys_out, 1, o, v, h & 0xFFFFu);
-                    if (has_pay) store_item(a.pay_out, a.pay_es, o, v, lo32(e[j]));
-                    if (a.perm_out) store_item(a.perm_out, 1, o, v, (int32_t)(h >> 16));
+                    if (a.keys_out) store_item<NTS>(a.keys_out, 1, o, v, h & 0xFFFFu);
+                    if (has_pay) store_item<NTS>(a.pay_out, a.pay_es, o, v, lo32(e[j]));
+                    if (a.perm_out) store_item<NTS>(a.perm_out, 1, o, v, (int32_t)(h >> 16));
                 } else {
-                    if (a.keys_out) store_item(a.keys_out, 1, o, v, a.f32 ? ordered_to_f32(h) : h);
-                    if (a.perm_out) store_item(a.perm_out, 1, o, v, (int32_t)lo32(e[j]));
+                    if (a.keys_out) store_item<NTS>(a.keys_out, 1, o, v, a.f32 ? ordered_to_f32(h) : h);
+                    if (a.perm_out) store_item<NTS>(a.perm_out, 1, o, v, (int32_t)lo32(e[j]));
                 }
             }
         }
-        if (!PREFETCH) issue_tile_load<CPW, CAP>(a, offs, t + gridDim.x, w, lane, L);
+        if (!PREFETCH) issue_tile_load<CPW, CAP, NTL>(a, offs, t + gridDim.x, w, lane, L);
     }
 }
 
-// Two tiles per workgroup in lockstep: every barrier of a pass serves both tiles, so
-// the per-tile synchronisation cost halves and each wave can keep twice the items in
-// registers (the workgroup holds 2 x CAP items of LDS).  Same splits as split_kernel.
-template <int NW, int CAP, int MODE>
-__global__ __launch_bounds__(NW * 64) void split2_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
-    constexpr int CPW = CAP / 64 / NW;
-    constexpr int N = CAP;
-    constexpr bool PREFETCH = CPW <= 8;
-    __shared__ uint64_t A[2][CAP];
-    __shared__ int wz[2][NW];
-    const int lane = lane_id();
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const uint32_t lmask = (MODE == 0) ? (1u << a.nbits) - 1u : 0xFFFFFFFFu;
-    const bool has_pay = a.has_pay != 0;
-    const int64_t pairs = (a.num_tiles + 1) / 2;
-
-    TileLoad<CPW> L[2];
-    int64_t g = blockIdx.x;
-    issue_tile_load<CPW, CAP>(a, offs, 2 * g, w, lane, L[0]);
-    issue_tile_load<CPW, CAP>(a, offs, 2 * g + 1, w, lane, L[1]);
-
-    for (; g < pairs; g += gridDim.x) {
-        int64_t o[2];
-        int n[2];
-        uint64_t e[2][CPW];
-        bool bad = false;
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-            o[tt] = L[tt].o;
-            n[tt] = L[tt].n;
-            if (n[tt] == -2) {
-                if (threadIdx.x == 0) atomicOr(a.err, ERR_TILE_TOO_LONG);
-                n[tt] = -1;  // skipped: nothing is stored
-            }
-#pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-                const int i = 64 * (w * CPW + j) + lane;
-                uint32_t lab = lmask, pay = 0;
-                if (i < n[tt]) {
-                    lab = L[tt].lab[j];
-                    if (MODE == 0) {
-                        bad |= lab >= a.num_classes;
-                        lab &= lmask;
-                        pay = L[tt].pay[j];
-                    } else if (a.f32) {
-                        lab = f32_to_ordered(lab);
-                    }
-                }
-                e[tt][j] = (MODE == 0) ? pack(((uint32_t)i << 16) | lab, pay) : pack(lab, (uint32_t)i);
-            }
-        }
-        if (a.validate) flag_error(a.err, bad, ERR_BAD_LABEL);
-        if (PREFETCH) {
-            issue_tile_load<CPW, CAP>(a, offs, 2 * (g + gridDim.x), w, lane, L[0]);
-            issue_tile_load<CPW, CAP>(a, offs, 2 * (g + gridDim.x) + 1, w, lane, L[1]);
-        }
-
-        const uint32_t lane8 = (uint32_t)lane * 8u;
-        const uint32_t neg_lane8 = 0u - lane8;
-        const uint32_t fwd_base = lane8 + (uint32_t)(w * CPW * 512);
-        for (int b = 0; b < a.nbits; ++b) {
-            int zc[2] = {0, 0};
-#pragma unroll
-            for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-                for (int j = 0; j < CPW; ++j) zc[tt] += 64 - popc64(ballot((hi32(e[tt][j]) >> b) & 1u));
-            if (lane == 0) {
-                wz[0][w] = zc[0];
-                wz[1][w] = zc[1];
-            }
-            __syncthreads();  // every wave has read the previous pass and posted its counts
-            int zb[2] = {0, 0}, zt[2] = {0, 0};
-#pragma unroll
-            for (int tt = 0; tt < 2; ++tt) {
-                const int mine = (lane < NW) ? wz[tt][lane] : 0;
-#pragma unroll
-                for (int q = 0; q < NW; ++q) {
-                    const int v = __builtin_amdgcn_readlane(mine, q);
-                    zt[tt] += v;
-                    zb[tt] += (q < w) ? v : 0;
-                }
-            }
-            bool run[2];
-#pragma unroll
-            for (int tt = 0; tt < 2; ++tt) {
-                // nothing to do for an absent tile, or when every item has the same bit
-                run[tt] = n[tt] > 0 && !(MODE == 1 && (zt[tt] == 0 || zt[tt] == N));
-                if (!run[tt]) continue;
-                int z = zb[tt];
-#pragma unroll
-                for (int j = 0; j < CPW; ++j) {
-                    const int k = w * CPW + j;
-                    const uint64_t bj = ballot((hi32(e[tt][j]) >> b) & 1u);
-                    const uint32_t r0 = count_below(~bj);
-                    const uint32_t z8 = (uint32_t)__builtin_amdgcn_readfirstlane(z * 8);
-                    const uint32_t o8 = (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 - 64 * k + z) * 8);
-                    const uint32_t a0 = r0 * 8u + z8;
-                    const uint32_t a1 = (r0 * 8u + neg_lane8) + o8;
-                    lds_store(A[tt], select_by_mask(bj, a0, a1), e[tt][j]);
-                    z += 64 - popc64(bj);
-                }
-            }
-            __syncthreads();  // both split tiles are complete
-#pragma unroll
-            for (int tt = 0; tt < 2; ++tt) {
-                if (!run[tt]) continue;
-                const int ztt = zt[tt];
-                const uint32_t rev_base =
-                    (uint32_t)__builtin_amdgcn_readfirstlane((N - 1 + ztt - 64 * w * CPW - 64 * (CPW - 1)) * 8) +
-                    neg_lane8;
-#pragma unroll
-                for (int j = 0; j < CPW; ++j) {
-                    const int base = 64 * (w * CPW + j);
-                    if (base + 64 <= ztt) {
-                        e[tt][j] = lds_load(A[tt], fwd_base + 512u * j);
-                    } else if (base >= ztt) {
-                        e[tt][j] = lds_load(A[tt], rev_base + 512u * (CPW - 1 - j));
-                    } else {
-                        e[tt][j] = lds_load(A[tt], (lane < ztt - base) ? fwd_base + 512u * j
-                                                                   : rev_base + 512u * (CPW - 1 - j));
-                    }
-                }
-            }
-        }
-
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-#pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-                const int v = 64 * (w * CPW + j) + lane;
-                if (v < n[tt]) {
-                    const uint32_t h = hi32(e[tt][j]);
-                    if (MODE == 0) {
-                        if (a.keys_out) store_item(a.keys_out, 1, o[tt], v, h & 0xFFFFu);
-                        if (has_pay) store_item(a.pay_out, a.pay_es, o[tt], v, lo32(e[tt][j]));
-                        if (a.perm_out) store_item(a.perm_out, 1, o[tt], v, (int32_t)(h >> 16));
-                    } else {
-                        if (a.keys_out) store_item(a.keys_out, 1, o[tt], v, a.f32 ? ordered_to_f32(h) : h);
-                        if (a.perm_out) store_item(a.perm_out, 1, o[tt], v, (int32_t)lo32(e[tt][j]));
-                    }
-                }
-            }
-        }
-        if (!PREFETCH) {
-            issue_tile_load<CPW, CAP>(a, offs, 2 * (g + gridDim.x), w, lane, L[0]);
-            issue_tile_load<CPW, CAP>(a, offs, 2 * (g + gridDim.x) + 1, w, lane, L[1]);
-        }
-    }
-}
-
-template <int NW, int CAP, int MODE>
-hipError_t launch_split2(const SplitArgs& a, const int64_t* offs, hipStream_t s) {
-    auto kern = split2_kernel<NW, CAP, MODE>;
-    const int grid = persistent_grid((const void*)kern, NW * 64, 0, (a.num_tiles + 1) / 2);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, offs);
-    return hipGetLastError();
-}
-
-template <int NW, int CAP, int WPE = 0, int MODE = 0, int PF = -1>
+// ONESHOT: one workgroup per tile (the hardware dispatcher overlaps the tiles of the
+// workgroups resident on a CU) instead of a persistent grid.
+template <int NW, int CAP, int WPE = 0, int MODE = 0, int PF = -1, int NTM = 0, bool ONESHOT = false>
 hipError_t launch_split(const SplitArgs& a, const int64_t* offs, hipStream_t s) {
-    auto kern = split_kernel<NW, CAP, WPE, MODE, PF>;
-    const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
+    auto kern = split_kernel<NW, CAP, WPE, MODE, PF, NTM>;
+    const int grid = ONESHOT ? (int)std::min<int64_t>(a.num_tiles, INT32_MAX)
+                             : persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, offs);
     return hipGetLastError();
+}
+
+// Launch shape for the kernels without a tuned variant table (tuning knob "oneshot"):
+// 1 (default) one workgroup per tile with streaming global accesses, 0 a persistent
+// grid that loads the next tile while it splits the current one.
+int g_oneshot = 1;
+
+template <int NW, int CAP, int WPE = 0, int MODE = 0>
+hipError_t launch_split_shaped(const SplitArgs& a, const int64_t* offs, hipStream_t s) {
+    return g_oneshot ? launch_split<NW, CAP, WPE, MODE, 0, 3, true>(a, offs, s)
+                     : launch_split<NW, CAP, WPE, MODE>(a, offs, s);
 }
 
 }  // namespace
 
+void set_oneshot(int v) { g_oneshot = v; }
+bool tile_oneshot() { return g_oneshot != 0; }
+
 int64_t partition_split_capacity() { return 16384; }
 
-// Kernel variant for 4096-item tiles (tuning knob): wave count, or 1xx = 8/4 waves with
-// a register cap; the default fits three workgroups per CU.
-static int g_part_nw4096 = 106;
+// Kernel variant for 4096-item tiles (tuning knob "partition_waves_4096"); the default
+// is one 8-wave workgroup per tile, four resident per CU.
+static int g_part_nw4096 = 168;
 void set_partition_waves(int nw) { g_part_nw4096 = nw; }
 
 hipError_t launch_partition_split(const PartitionArgs& p, int64_t max_len, hipStream_t s) {
@@ -411,28 +277,28 @@ hipError_t launch_partition_split(const PartitionArgs& p, int64_t max_len, hipSt
     a.validate = p.validate;
     a.err = p.err;
     const int64_t* o = p.offsets;
-    if (max_len <= 1024) return launch_split<4, 1024>(a, o, s);
-    if (max_len <= 2048) return launch_split<4, 2048>(a, o, s);
+    if (max_len <= 1024) return launch_split_shaped<4, 1024>(a, o, s);
+    if (max_len <= 2048) return launch_split_shaped<4, 2048>(a, o, s);
     if (max_len <= 4096) {
         switch (g_part_nw4096) {
             case 1: return launch_split<1, 4096>(a, o, s);
             case 2: return launch_split<2, 4096>(a, o, s);
             case 4: return launch_split<4, 4096>(a, o, s);
             case 16: return launch_split<16, 4096>(a, o, s);
-            case 108: return launch_split<8, 4096, 8>(a, o, s);   // 8 waves, 4 workgroups per CU
-            case 110: return launch_split<8, 4096, 10>(a, o, s);  // 8 waves, 5 workgroups per CU
-            case 104: return launch_split<4, 4096, 4>(a, o, s);   // 4 waves, 4 workgroups per CU
-            case 118: return launch_split<8, 4096, -1>(a, o, s);  // 8 waves, no prefetch
-            case 106: return launch_split<8, 4096, 6, 0, 1>(a, o, s);  // 3 workgroups per CU, prefetch
-            case 116: return launch_split<8, 4096, 6, 0, 0>(a, o, s);  // 3 workgroups per CU
-            case 208: return launch_split2<8, 4096, 0>(a, o, s);  // two tiles per workgroup
-            case 204: return launch_split2<4, 4096, 0>(a, o, s);
-            case 216: return launch_split2<16, 4096, 0>(a, o, s);
-            default: return launch_split<8, 4096>(a, o, s);
+            // persistent grids: 1xx = 8 or 4 waves with registers capped for xx/2 waves per SIMD
+            case 104: return launch_split<4, 4096, 4>(a, o, s);         // 4 waves, 4 workgroups per CU
+            case 106: return launch_split<8, 4096, 6, 0, 1>(a, o, s);   // 3 workgroups per CU, prefetch
+            case 108: return launch_split<8, 4096, 8>(a, o, s);         // 4 workgroups per CU
+            // one workgroup per tile, streaming loads and stores (176: plain accesses)
+            case 164: return launch_split<4, 4096, 4, 0, 0, 3, true>(a, o, s);
+            case 166: return launch_split<8, 4096, 6, 0, 0, 3, true>(a, o, s);
+            case 168: return launch_split<8, 4096, 8, 0, 0, 3, true>(a, o, s);
+            case 176: return launch_split<8, 4096, 6, 0, 0, 0, true>(a, o, s);
+            default: return launch_split_shaped<8, 4096>(a, o, s);
         }
     }
-    if (max_len <= 8192) return launch_split<8, 8192>(a, o, s);
-    return launch_split<16, 16384>(a, o, s);
+    if (max_len <= 8192) return launch_split_shaped<8, 8192>(a, o, s);
+    return launch_split_shaped<16, 16384>(a, o, s);
 }
 
 hipError_t launch_sort_split(const SortArgs& q, int64_t max_len, hipStream_t s) {
@@ -446,11 +312,11 @@ hipError_t launch_sort_split(const SortArgs& q, int64_t max_len, hipStream_t s) 
     a.f32 = q.f32;
     a.err = q.err;
     const int64_t* o = q.offsets;
-    if (max_len <= 1024) return launch_split<4, 1024, 0, 1>(a, o, s);
-    if (max_len <= 2048) return launch_split<4, 2048, 0, 1>(a, o, s);
-    if (max_len <= 4096) return launch_split<8, 4096, 0, 1>(a, o, s);
-    if (max_len <= 8192) return launch_split<8, 8192, 0, 1>(a, o, s);
-    return launch_split<16, 16384, 0, 1>(a, o, s);
+    if (max_len <= 1024) return launch_split_shaped<4, 1024, 0, 1>(a, o, s);
+    if (max_len <= 2048) return launch_split_shaped<4, 2048, 0, 1>(a, o, s);
+    if (max_len <= 4096) return launch_split_shaped<8, 4096, 0, 1>(a, o, s);
+    if (max_len <= 8192) return launch_split_shaped<8, 8192, 0, 1>(a, o, s);
+    return launch_split_shaped<16, 16384, 0, 1>(a, o, s);
 }
 
 }  // namespace ts

@@ -10,6 +10,8 @@
 // bits of the high word, source in the high 16), so either direction can also write
 // the inverse permutation at no extra routing: a scatter's caller can then undo it
 // with another scatter instead of a two-routing gather.
+#include <algorithm>
+#include <cstdint>
 #include <type_traits>
 
 #include "common.hpp"
@@ -22,7 +24,7 @@ namespace {
 
 // REPLAY (for two or more payload channels): channel 0 is routed and recorded, the
 // other channels replay the record two per 64-bit item.
-template <int NW, int CAP, bool GATHER, int WPE, bool REPLAY>
+template <int NW, int CAP, bool GATHER, int WPE, bool REPLAY, bool NT>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
     using R = Router<NW, CAP>;
@@ -51,7 +53,7 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
         uint32_t dst[CPW];
         bool bad = false;
         int32_t piv[CPW];
-        load_columns<CPW>(a.pi, 1, o, n, w * CPW, lane, piv, offs);
+        load_columns<CPW, NT>(a.pi, 1, o, n, w * CPW, lane, piv, offs);
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
             const int i = 64 * (w * CPW + j) + lane;
@@ -76,7 +78,7 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
                 const uint64_t x = lds_load_u64_whole(A, own_base + 512u * j);
                 if (a.validate) flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)q, ERR_BAD_PERM);
                 dst[j] = lo32(x);  // inv[q] for q = 64k + l
-                if (a.inv_out && q < n) store_item(a.inv_out, 1, o, q, (int32_t)dst[j]);
+                if (a.inv_out && q < n) store_item<NT>(a.inv_out, 1, o, q, (int32_t)dst[j]);
             }
             __syncthreads();  // A is reused by the next routing
         } else {
@@ -99,7 +101,7 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
             const int64_t cbase = (int64_t)c * a.pay.cs;
             const bool with_pay = a.pay.channels > 0;
             uint32_t xv[CPW];
-            load_columns<CPW>(a.pay.in + (with_pay ? cbase : 0), a.pay.es, o, with_pay ? n : 0, w * CPW,
+            load_columns<CPW, NT>(a.pay.in + (with_pay ? cbase : 0), a.pay.es, o, with_pay ? n : 0, w * CPW,
                               lc, xv, offs);
 #pragma unroll
             for (int j = 0; j < CPW; ++j) e[j] = pack(dst[j], xv[j]);
@@ -112,8 +114,8 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
                 if (a.validate && c == 0 && !gather)
                     flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)v, ERR_BAD_PERM);
                 if (v < n) {
-                    if (with_pay) store_item(a.pay.out + cbase, a.pay.es, o, v, lo32(x));
-                    if (!gather && c == 0 && a.inv_out) store_item(a.inv_out, 1, o, v, (int32_t)(hi32(x) >> 16));
+                    if (with_pay) store_item<NT>(a.pay.out + cbase, a.pay.es, o, v, lo32(x));
+                    if (!gather && c == 0 && a.inv_out) store_item<NT>(a.inv_out, 1, o, v, (int32_t)(hi32(x) >> 16));
                 }
             }
             __syncthreads();  // A is reused by the next channel / tile
@@ -127,8 +129,8 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
                 const int64_t cb0 = (int64_t)c * a.pay.cs;
                 const int64_t cb1 = two ? cb0 + a.pay.cs : cb0;
                 uint32_t x0[CPW], x1[CPW];
-                load_columns<CPW>(a.pay.in + cb0, a.pay.es, o, n, w * CPW, lc, x0, offs);
-                load_columns<CPW>(a.pay.in + cb1, a.pay.es, o, n, w * CPW, lc, x1, offs);
+                load_columns<CPW, NT>(a.pay.in + cb0, a.pay.es, o, n, w * CPW, lc, x0, offs);
+                load_columns<CPW, NT>(a.pay.in + cb1, a.pay.es, o, n, w * CPW, lc, x1, offs);
 #pragma unroll
                 for (int j = 0; j < CPW; ++j) e[j] = pack(x1[j], x0[j]);
                 R::replay(A, &plan, e, pdst, w, lane);
@@ -137,8 +139,8 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
                     const int v = 64 * (w * CPW + j) + lc;
                     const uint64_t x = lds_load_u64_whole(A, own_c + 512u * j);
                     if (v < n) {
-                        store_item(a.pay.out + cb0, a.pay.es, o, v, lo32(x));
-                        if (two) store_item(a.pay.out + cb1, a.pay.es, o, v, hi32(x));
+                        store_item<NT>(a.pay.out + cb0, a.pay.es, o, v, lo32(x));
+                        if (two) store_item<NT>(a.pay.out + cb1, a.pay.es, o, v, hi32(x));
                     }
                 }
                 __syncthreads();  // A is reused by the next pair / tile
@@ -147,37 +149,51 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
     }
 }
 
-template <int NW, int CAP, int WPE = 0>
+// ONESHOT: one workgroup per tile instead of a persistent grid; NT: streaming global
+// loads and stores (every word is read or written once).
+template <int NW, int CAP, int WPE = 0, bool ONESHOT = false, bool NT = false>
 hipError_t launch_perm(const PermuteArgs& a, hipStream_t s) {
     const bool replay = a.pay.channels >= 2;
     auto kern = (a.direction == 1)
-                    ? (replay ? permute_split_kernel<NW, CAP, true, WPE, true>
-                              : permute_split_kernel<NW, CAP, true, WPE, false>)
-                    : (replay ? permute_split_kernel<NW, CAP, false, WPE, true>
-                              : permute_split_kernel<NW, CAP, false, WPE, false>);
-    const int grid = persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
+                    ? (replay ? permute_split_kernel<NW, CAP, true, WPE, true, NT>
+                              : permute_split_kernel<NW, CAP, true, WPE, false, NT>)
+                    : (replay ? permute_split_kernel<NW, CAP, false, WPE, true, NT>
+                              : permute_split_kernel<NW, CAP, false, WPE, false, NT>);
+    const int grid = ONESHOT ? (int)std::min<int64_t>(a.num_tiles, INT32_MAX)
+                             : persistent_grid((const void*)kern, NW * 64, 0, a.num_tiles);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, a, a.offsets);
     return hipGetLastError();
+}
+
+template <int NW, int CAP, int WPE = 0>
+hipError_t launch_perm_shaped(const PermuteArgs& a, hipStream_t s) {
+    return tile_oneshot() ? launch_perm<NW, CAP, WPE, true, true>(a, s) : launch_perm<NW, CAP, WPE>(a, s);
 }
 
 }  // namespace
 
 int64_t permute_split_capacity() { return 16384; }
 
-// Kernel variant for 8192-item tiles (tuning knob): 0 = 16 waves, registers as the
-// compiler likes; 1 = 16 waves capped at 64 registers (two workgroups per CU).
-static int g_perm_variant = 0;
+// Kernel variant for 8192-item tiles (tuning knob "permute_variant").  Persistent grids:
+// 0 = 16 waves, registers as the compiler likes; 1 = 16 waves capped at 64 registers
+// (two workgroups per CU); 2 = 8 waves.  One workgroup per tile, 16 waves capped at 64
+// registers: 6 = streaming loads and stores (default), 7 = plain accesses; 8 = the
+// persistent form of 6.
+static int g_perm_variant = 6;
 void set_permute_variant(int v) { g_perm_variant = v; }
 
 hipError_t launch_permute_split(const PermuteArgs& a, int64_t max_len, hipStream_t s) {
     if (a.num_tiles == 0) return hipSuccess;
-    if (max_len <= 4096) return g_perm_variant == 1 ? launch_perm<8, 4096, 6>(a, s) : launch_perm<8, 4096>(a, s);
+    if (max_len <= 4096) return g_perm_variant == 1 ? launch_perm_shaped<8, 4096, 6>(a, s) : launch_perm_shaped<8, 4096>(a, s);
     if (max_len <= 8192) {
         if (g_perm_variant == 1) return launch_perm<16, 8192, 8>(a, s);
         if (g_perm_variant == 2) return launch_perm<8, 8192>(a, s);
+        if (g_perm_variant == 6) return launch_perm<16, 8192, 8, true, true>(a, s);
+        if (g_perm_variant == 7) return launch_perm<16, 8192, 8, true, false>(a, s);
+        if (g_perm_variant == 8) return launch_perm<16, 8192, 8, false, true>(a, s);
         return launch_perm<16, 8192>(a, s);
     }
-    return launch_perm<16, 16384>(a, s);
+    return launch_perm_shaped<16, 16384>(a, s);
 }
 
 }  // namespace ts

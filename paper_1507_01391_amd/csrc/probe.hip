@@ -1,6 +1,8 @@
 // Measurement kernels: an LDS access probe (bank count, width and phase
 // behaviour of gfx950 LDS, read by the SQ_LDS_BANK_CONFLICT counter and by
 // s_memtime) and a plain HBM copy (the achievable-bandwidth reference).
+#include <cstdint>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -137,24 +139,25 @@ hipError_t launch_probe_t(const uint32_t* lane_words, int iters, int waves, int 
     return hipGetLastError();
 }
 
-// Grid-stride copy, four independent 16-byte loads in flight per thread.
+// Copy: every workgroup moves one contiguous chunk of 256 x COPY_U 16-byte vectors with
+// streaming loads and stores, all loads issued before the first store; the last
+// chunk may be partial.
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+constexpr int COPY_U = 8;
+constexpr size_t COPY_CHUNK = 256 * COPY_U;
 
 __global__ __launch_bounds__(256) void copy_kernel(const v4u* __restrict__ src,
                                                    v4u* __restrict__ dst, size_t n16) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        const v4u a = __builtin_nontemporal_load(src + i);
-        const v4u b = __builtin_nontemporal_load(src + i + stride);
-        const v4u c = __builtin_nontemporal_load(src + i + 2 * stride);
-        const v4u d = __builtin_nontemporal_load(src + i + 3 * stride);
-        __builtin_nontemporal_store(a, dst + i);
-        __builtin_nontemporal_store(b, dst + i + stride);
-        __builtin_nontemporal_store(c, dst + i + 2 * stride);
-        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    const size_t c = (size_t)blockIdx.x * COPY_CHUNK;
+    if (c + COPY_CHUNK <= n16) {
+        v4u r[COPY_U];
+#pragma unroll
+        for (int u = 0; u < COPY_U; ++u) r[u] = __builtin_nontemporal_load(src + c + u * 256 + threadIdx.x);
+#pragma unroll
+        for (int u = 0; u < COPY_U; ++u) __builtin_nontemporal_store(r[u], dst + c + u * 256 + threadIdx.x);
+    } else {
+        for (size_t i = c + threadIdx.x; i < n16; i += 256) dst[i] = src[i];
     }
-    for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 __global__ void copy_tail_kernel(const uint8_t* src, uint8_t* dst, size_t n) {
@@ -185,8 +188,9 @@ hipError_t launch_lds_probe(const uint32_t* lane_words, int op, int width, int i
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
     const size_t n16 = bytes / 16;
     if (n16) {
-        const int grid = num_cus() * 16;
-        hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, s, (const v4u*)src, (v4u*)dst, n16);
+        const size_t grid = (n16 + COPY_CHUNK - 1) / COPY_CHUNK;
+        if (grid > (size_t)INT32_MAX) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)grid), dim3(256), 0, s, (const v4u*)src, (v4u*)dst, n16);
     }
     const size_t tail = bytes - n16 * 16;
     if (tail) {

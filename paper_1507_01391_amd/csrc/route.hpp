@@ -47,66 +47,91 @@ struct Router {
         int zb[6][NW];           // zeros of the segment before each wave's first column
     };
 
-    // Route e[] (column w*CPW + j of the current order in e[j]) so that on return the
-    // LDS array A holds every item at its destination slot.  Contains barriers: every
-    // wave of the workgroup must call it.  With RECORD the routing is written to *plan
-    // and pdst[j] receives the slot of the item this lane places in step w*CPW + j.
-    template <bool RECORD = false>
-    static TS_DEV void route(uint64_t* A, int* wz, uint64_t (&e)[CPW], int w, int lane,
-                             Plan* plan = nullptr, uint32_t* pdst = nullptr) {
-#pragma unroll 1
-        for (int L = 0; L < 6; ++L) {
-            const uint32_t lane8 = opaque((uint32_t)lane * 8u);
-            const uint32_t neg_lane8 = 0u - lane8;
-            const uint32_t own_base = lane8 + (uint32_t)(w * CPW * 512);  // column j at + 512 j
-            const int bit = 5 - L;                 // bank bit split at this level
-            const int seg_cols = NCOL >> L;        // columns per segment
-            const bool shared = seg_cols > CPW;    // segment spans several waves
-            int zb = 0;  // zeros of this segment in columns before this wave's first column
-            if (shared) {
+    // One binary split (level L, bank bit 5 - L) of every segment.  MODE 0: route;
+    // 1: route and record into *plan; 2: replay the split recorded in *plan.
+    //
+    // Column k (k_in = k mod segment columns) writes a zero to seg_base + z + r0 and a one
+    // to seg_end - 1 - (64 k_in - z) - (lane - r0), z the segment's zeros before the
+    // column and r0 the zeros in lower lanes; i.e. to seg_base + z + r0 +
+    // (one ? 64 (seg_cols - k_in) - 1 - lane : 0), the bracket folded into the rank count.
+    template <int L, int MODE>
+    static TS_DEV void split_level(uint64_t* A, int* wz, uint64_t (&e)[CPW], int w, int lane, Plan* plan) {
+        constexpr int bit = 5 - L;                 // bank bit split at this level
+        constexpr int seg_cols = NCOL >> L;        // columns per segment
+        constexpr bool shared = seg_cols > CPW;    // segment spans several waves
+        constexpr bool keep = CPW <= 8;            // zero masks kept between the two loops
+        const uint32_t lane8 = opaque((uint32_t)lane * 8u);
+        const uint32_t own_base = lane8 + (uint32_t)(w * CPW * 512);  // column j at + 512 j
+        auto zero_mask = [&](int j) -> uint64_t {
+            if constexpr (MODE == 2) {
+                const uint64_t bv = plan->bal[L][w * CPW + j];  // same word for every lane
+                // (readfirstlane returns a signed int: widen through uint32_t)
+                return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(hi32(bv)) << 32) |
+                       (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(lo32(bv));
+            } else {
+                return ballot(((hi32(e[j]) >> bit) & 1u) == 0u);
+            }
+        };
+        uint64_t zm[keep ? CPW : 1];
+        int zb = 0;  // zeros of this segment in columns before this wave's first column
+        if constexpr (shared) {
+            if constexpr (MODE == 2) {
+                zb = (int)__builtin_amdgcn_readfirstlane((uint32_t)plan->zb[L][w]);
+                __syncthreads();  // every wave has read the previous level
+            } else {
                 int zc = 0;
 #pragma unroll
-                for (int j = 0; j < CPW; ++j) zc += 64 - popc64(ballot((hi32(e[j]) >> bit) & 1u));
+                for (int j = 0; j < CPW; ++j) {
+                    const uint64_t m = zero_mask(j);
+                    if constexpr (keep) zm[j] = m;
+                    zc += popc64(m);
+                }
                 if (lane == 0) wz[w] = zc;
                 __syncthreads();  // all waves have read the previous level and posted counts
-                const int waves_per_seg = seg_cols / CPW;
-                const int first = (w / waves_per_seg) * waves_per_seg;
-                const int mine = (lane < NW) ? wz[lane] : 0;
-#pragma unroll
-                for (int q = 0; q < NW; ++q) {
-                    const int v = __builtin_amdgcn_readlane(mine, q);
-                    zb += (q >= first && q < w) ? v : 0;
-                }
-                if (RECORD && lane == 0) plan->zb[L][w] = zb;
+                // lanes first .. w-1 (the earlier waves of this wave's segment) hold their
+                // counts; a prefix sum over the first NW lanes adds them up
+                constexpr int wps = seg_cols / CPW;  // waves per segment (a power of two)
+                const int first = w & ~(wps - 1);
+                const uint32_t mine = (lane >= first && lane < w) ? (uint32_t)wz[lane] : 0u;
+                zb = (int)__builtin_amdgcn_readlane((int)row_prefix_sum<NW>(mine), NW - 1);
+                if (MODE == 1 && lane == 0) plan->zb[L][w] = zb;
             }
-            if (!shared) wave_lds_fence();  // the previous level's reads stay before these writes
-            int z = zb;
-#pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-                const int k = w * CPW + j;         // global column
-                const int kin = k % seg_cols;      // column inside its segment
-                if (!shared && kin == 0) z = 0;    // a new wave-local segment starts
-                const int seg_base = k - kin;      // first column of the segment
-                // ballot recomputed here rather than kept from the count loop (registers)
-                const uint64_t bal = ballot((hi32(e[j]) >> bit) & 1u);
-                if (RECORD && lane == 0) plan->bal[L][k] = bal;
-                const uint32_t r0 = count_below(~bal);
-                // zero: seg_base*64 + z + rank0; one: seg_end - 1 - (64 kin - z) - (lane - rank0)
-                const uint32_t z8 = (uint32_t)__builtin_amdgcn_readfirstlane((seg_base * 64 + z) * 8);
-                const uint32_t d8 = (uint32_t)__builtin_amdgcn_readfirstlane((seg_cols * 64 - 1 - 64 * kin) * 8);
-                const uint32_t a0 = r0 * 8u + z8;
-                const uint32_t a1 = a0 + neg_lane8 + d8;
-                lds_store(A, select_by_mask(bal, a0, a1), e[j]);
-                z += 64 - popc64(bal);
-            }
-            if (shared) __syncthreads();  // the level is complete in every segment
-            else wave_lds_fence();
-#pragma unroll
-            for (int j = 0; j < CPW; ++j) e[j] = lds_load(A, own_base + 512u * j);
+        } else {
+            wave_lds_fence();  // the previous level's reads stay before these writes
         }
-        // ---- placement: group g = slots [g*M, (g+1)*M) holds the items for bank g.
-        //      Wave w performs steps t = w*CPW + j; lane l reads item (t + l) mod M of
-        //      group l and later writes it to its destination (bank l).
+        int z = zb;
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            const int k = w * CPW + j;                          // global column
+            const int kin = shared ? (k & (seg_cols - 1)) : (j & (seg_cols - 1));
+            if (!shared && kin == 0) z = 0;                     // a new wave-local segment
+            const uint64_t m = (keep && shared && MODE != 2) ? zm[keep ? j : 0] : zero_mask(j);
+            if (MODE == 1 && lane == 0) plan->bal[L][k] = m;
+            const uint32_t one_off = zero_if_mask(m, (uint32_t)(64 * (seg_cols - kin) - 1) - (uint32_t)lane);
+            const uint32_t pos = count_below_plus(m, one_off) + (uint32_t)(64 * (k - kin) + z);
+            lds_store(A, pos * 8u, e[j]);
+            z += popc64(m);
+        }
+        if (shared) __syncthreads();  // the level is complete in every segment
+        else wave_lds_fence();
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) e[j] = lds_load(A, own_base + 512u * j);
+    }
+
+    template <int MODE>
+    static TS_DEV void split_levels(uint64_t* A, int* wz, uint64_t (&e)[CPW], int w, int lane, Plan* plan) {
+        split_level<0, MODE>(A, wz, e, w, lane, plan);
+        split_level<1, MODE>(A, wz, e, w, lane, plan);
+        split_level<2, MODE>(A, wz, e, w, lane, plan);
+        split_level<3, MODE>(A, wz, e, w, lane, plan);
+        split_level<4, MODE>(A, wz, e, w, lane, plan);
+        split_level<5, MODE>(A, wz, e, w, lane, plan);
+    }
+
+    // Placement: group g = slots [g*M, (g+1)*M) holds the items for bank g.  Wave w
+    // performs steps t = w*CPW + j; lane l reads item (t + l) mod M of group l and then
+    // writes it to its destination (bank l).
+    static TS_DEV void gather_groups(const uint64_t* A, uint64_t (&e)[CPW], int w, int lane) {
         __syncthreads();  // every wave's groups are complete
         const int lane_o = (int)opaque((uint32_t)lane);
 #pragma unroll
@@ -116,6 +141,17 @@ struct Router {
             e[j] = lds_load(A, slot * 8u);
         }
         __syncthreads();  // all groups read before any slot is overwritten
+    }
+
+    // Route e[] (column w*CPW + j of the current order in e[j]) so that on return the
+    // LDS array A holds every item at its destination slot.  Contains barriers: every
+    // wave of the workgroup must call it.  With RECORD the routing is written to *plan
+    // and pdst[j] receives the slot of the item this lane places in step w*CPW + j.
+    template <bool RECORD = false>
+    static TS_DEV void route(uint64_t* A, int* wz, uint64_t (&e)[CPW], int w, int lane,
+                             Plan* plan = nullptr, uint32_t* pdst = nullptr) {
+        split_levels<RECORD ? 1 : 0>(A, wz, e, w, lane, plan);
+        gather_groups(A, e, w, lane);
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
             const uint32_t dst = hi32(e[j]) & (uint32_t)(CAP - 1);
@@ -130,53 +166,8 @@ struct Router {
     // Contains barriers: every wave of the workgroup must call it.
     static TS_DEV void replay(uint64_t* A, const Plan* plan, uint64_t (&e)[CPW],
                               const uint32_t* pdst, int w, int lane) {
-#pragma unroll 1
-        for (int L = 0; L < 6; ++L) {
-            const uint32_t lane8 = opaque((uint32_t)lane * 8u);
-            const uint32_t neg_lane8 = 0u - lane8;
-            const uint32_t own_base = lane8 + (uint32_t)(w * CPW * 512);
-            const int seg_cols = NCOL >> L;
-            const bool shared = seg_cols > CPW;
-            int zb = 0;
-            if (shared) {
-                zb = (int)__builtin_amdgcn_readfirstlane((uint32_t)plan->zb[L][w]);
-                __syncthreads();  // every wave has read the previous level
-            } else {
-                wave_lds_fence();
-            }
-            int z = zb;
-#pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-                const int k = w * CPW + j;
-                const int kin = k % seg_cols;
-                if (!shared && kin == 0) z = 0;
-                const int seg_base = k - kin;
-                const uint64_t bv = plan->bal[L][k];  // same word for every lane
-                // (readfirstlane returns a signed int: widen through uint32_t)
-                const uint64_t bal = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(hi32(bv)) << 32) |
-                                     (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(lo32(bv));
-                const uint32_t r0 = count_below(~bal);
-                const uint32_t z8 = (uint32_t)__builtin_amdgcn_readfirstlane((seg_base * 64 + z) * 8);
-                const uint32_t d8 = (uint32_t)__builtin_amdgcn_readfirstlane((seg_cols * 64 - 1 - 64 * kin) * 8);
-                const uint32_t a0 = r0 * 8u + z8;
-                const uint32_t a1 = a0 + neg_lane8 + d8;
-                lds_store(A, select_by_mask(bal, a0, a1), e[j]);
-                z += 64 - popc64(bal);
-            }
-            if (shared) __syncthreads();
-            else wave_lds_fence();
-#pragma unroll
-            for (int j = 0; j < CPW; ++j) e[j] = lds_load(A, own_base + 512u * j);
-        }
-        __syncthreads();
-        const int lane_o = (int)opaque((uint32_t)lane);
-#pragma unroll
-        for (int j = 0; j < CPW; ++j) {
-            const int t = w * CPW + j;
-            const uint32_t slot = (uint32_t)lane_o * M + (uint32_t)((t + lane_o) & (M - 1));
-            e[j] = lds_load(A, slot * 8u);
-        }
-        __syncthreads();
+        split_levels<2>(A, nullptr, e, w, lane, const_cast<Plan*>(plan));
+        gather_groups(A, e, w, lane);
 #pragma unroll
         for (int j = 0; j < CPW; ++j) lds_store(A, pdst[j] * 8u, e[j]);
         __syncthreads();

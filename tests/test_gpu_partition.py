@@ -50,19 +50,26 @@ def test_uneven_tiles_random_labels(ts, oracle, schedule, num_classes):
 
 @pytest.mark.parametrize("schedule", ["split", "naive"])
 @pytest.mark.parametrize("cap", [1024, 2048, 8192, 16384])
-def test_large_tiles(ts, oracle, schedule, cap):
+@pytest.mark.parametrize("oneshot", [1, 0])
+def test_large_tiles(ts, oracle, schedule, cap, oneshot):
     rng = np.random.default_rng(cap)
     sizes = np.array([cap, cap - 1, cap // 2 + 7, 1, 0, cap])
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     labels = rng.integers(0, 64, size=off[-1], dtype=np.uint32)
     payload = rng.integers(0, 2**32, size=off[-1], dtype=np.uint32)
-    run_and_compare(ts, oracle, labels, payload, off, 64, schedule, max_len=cap)
+    knob = "oneshot" if schedule == "split" else "naive_oneshot"
+    prev = ts.knob(knob, 1 if schedule == "split" else 0)
+    ts.tune(knob, oneshot)
+    try:
+        run_and_compare(ts, oracle, labels, payload, off, 64, schedule, max_len=cap)
+    finally:
+        ts.tune(knob, prev)
 
 
-@pytest.mark.parametrize("waves", [1, 2, 4, 8, 16, 104, 106, 108, 110, 116, 118, 204, 208, 216])
+@pytest.mark.parametrize("waves", [1, 2, 4, 8, 16, 104, 106, 108, 164, 166, 168, 176])
 def test_wave_count_variants(ts, oracle, waves):
     labels, payload, off = inputs.partition(seed=30 + waves, num_tiles=40, n=4096)
-    prev = ts.knob("partition_waves_4096", 106)
+    prev = ts.knob("partition_waves_4096", 168)
     ts.tune("partition_waves_4096", waves)
     try:
         run_and_compare(ts, oracle, labels, payload, off, 64, "split", max_len=4096)

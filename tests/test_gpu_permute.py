@@ -33,13 +33,19 @@ def test_families_8192(ts, oracle, direction, family, schedule):
 
 @pytest.mark.parametrize("direction", ["scatter", "gather"])
 @pytest.mark.parametrize("cap", [4096, 8192, 16384])
-def test_uneven_tiles(ts, oracle, direction, cap):
+@pytest.mark.parametrize("oneshot", [1, 0])
+def test_uneven_tiles(ts, oracle, direction, cap, oneshot):
     rng = np.random.default_rng(cap + (direction == "gather"))
     sizes = np.concatenate([[0, 1, 2, 63, 64, 65, cap, cap - 1], rng.integers(0, cap + 1, size=20)])
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     x = rng.integers(0, 2**32, size=off[-1], dtype=np.uint32)
     pi = np.concatenate([rng.permutation(int(s)) for s in sizes]).astype(np.int32)
-    run_and_compare(ts, oracle, x, pi, off, direction, max_len=cap)
+    prev = ts.knob("oneshot", 1)
+    ts.tune("oneshot", oneshot)
+    try:
+        run_and_compare(ts, oracle, x, pi, off, direction, max_len=cap)
+    finally:
+        ts.tune("oneshot", prev)
 
 
 @pytest.mark.parametrize("direction", ["scatter", "gather"])
@@ -74,11 +80,11 @@ def test_validate_reports_non_permutation(ts, direction):
         ts.check_device_errors()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8])
 @pytest.mark.parametrize("direction", ["scatter", "gather"])
 def test_permute_variants(ts, oracle, variant, direction):
     x, pi, _, off = inputs.permutation(seed=43, num_tiles=24, n=8192, family="uniform")
-    prev = ts.knob("permute_variant", 0)
+    prev = ts.knob("permute_variant", 6)
     ts.tune("permute_variant", variant)
     try:
         run_and_compare(ts, oracle, x, pi, off, direction, max_len=8192)
@@ -142,11 +148,11 @@ def test_multichannel_replay(ts, oracle, channels, direction, cap):
     run_and_compare(ts, oracle, x, pi, off, direction, max_len=cap)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8])
 def test_multichannel_replay_variants(ts, oracle, variant):
     x, pi, _, off = inputs.permutation(seed=72, num_tiles=12, n=8192, family="transpose")
     x4 = np.stack([x, -x, 2 * x, x + 1]).astype(np.float32)
-    prev = ts.knob("permute_variant", 0)
+    prev = ts.knob("permute_variant", 6)
     ts.tune("permute_variant", variant)
     try:
         for direction in ("scatter", "gather"):
