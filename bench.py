@@ -235,9 +235,10 @@ def bench_c1(torch, ts, inputs):
 
 def bench_c3(args, torch, ts, inputs):
     """fwd + bwd permutation of 16384 tiles x 8192 fp32: forward y[pi[i]] = x[i], backward
-    dx[i] = dy[pi[i]] -- the conflict-free path writes pi^-1 during the forward routing
-    and runs the backward as a scatter by it (what autograd.Permute does); the naive
-    form scatters forward and gathers backward, one LDS pass each."""
+    dx[i] = dy[pi[i]] -- the conflict-free path writes pi^-1 (16-bit tile-local indices;
+    "inv32": int32) during the forward routing and runs the backward as a scatter by it
+    (what autograd.Permute does); the naive form scatters forward and gathers backward,
+    one LDS pass each.  GB/s count the algorithmic 24 B per element."""
     T = args.tiles3
     x, pi, g, off = inputs.permutation(num_tiles=T, n=8192)
     dx = torch.from_numpy(x).cuda()
@@ -246,13 +247,18 @@ def bench_c3(args, torch, ts, inputs):
     doff = torch.from_numpy(off).cuda()
     y = torch.empty_like(dx)
     gx = torch.empty_like(dx)
-    inv = torch.empty_like(dpi)
+    inv = torch.empty(dpi.shape, dtype=torch.int16, device=dpi.device)
+    inv32 = torch.empty_like(dpi)
     n = T * 8192
     out = {}
 
     def split_fwd_bwd():
         ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y, inv_out=inv)
         ts.tile_permute(dg, inv, "scatter", doff, max_tile_len=8192, out=gx)
+
+    def split_fwd_bwd_inv32():
+        ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y, inv_out=inv32)
+        ts.tile_permute(dg, inv32, "scatter", doff, max_tile_len=8192, out=gx)
 
     def split_scatter_gather():
         ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y)
@@ -262,7 +268,8 @@ def bench_c3(args, torch, ts, inputs):
         ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y, schedule="naive")
         ts.tile_permute(dg, dpi, "gather", doff, max_tile_len=8192, out=gx, schedule="naive")
 
-    for name, fn in (("split", split_fwd_bwd), ("split_scatter_plus_gather", split_scatter_gather),
+    for name, fn in (("split", split_fwd_bwd), ("split_inv32", split_fwd_bwd_inv32),
+                     ("split_scatter_plus_gather", split_scatter_gather),
                      ("naive", naive_fwd_bwd), ("naive_oneshot", naive_fwd_bwd)):
         ts.tune("naive_oneshot", 1 if name == "naive_oneshot" else 0)
         log(f"[bench] C3 fwd+bwd permute ({name}) ...")

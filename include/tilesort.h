@@ -76,7 +76,12 @@ enum {
     TS_FLAG_F32_ORDERED = 1u,
     /* kernels check labels / pi against the data contract and record violations
        (labels: every partition schedule; pi: the SPLIT permute schedule) */
-    TS_FLAG_VALIDATE = 2u
+    TS_FLAG_VALIDATE = 2u,
+    /* tile_permute: pi points to uint16 values (tile-local indices fit in 16 bits
+       for every supported tile length); halves the index bytes read */
+    TS_FLAG_PI_U16 = 4u,
+    /* tile_permute: inv_out receives uint16 values */
+    TS_FLAG_INV_U16 = 8u
 };
 
 /* Schedule selection, stored in flags bits 8..11 (TS_SCHED(x) = x << 8). */
@@ -150,6 +155,8 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
  *             inv_out[pi[i]] = i, computed by the same routing (no extra pass);
  *             a later GATHER by pi equals a SCATTER by inv_out, which routes once
  *             instead of twice.  Must not alias pi or in.
+ * With TS_FLAG_PI_U16 pi is read as uint16 [N], with TS_FLAG_INV_U16 inv_out is
+ * written as uint16 [N] (the pointers keep their declared types; cast them).
  * Supported tile length: max_tile_len <= 16384.
  */
 ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels,

@@ -15,6 +15,8 @@ TS_OK, TS_ERR_INVALID, TS_ERR_UNSUPPORTED, TS_ERR_HIP, TS_ERR_WORKSPACE = range(
 TS_SCATTER, TS_GATHER = 0, 1
 TS_FLAG_F32_ORDERED = 1
 TS_FLAG_VALIDATE = 2
+TS_FLAG_PI_U16 = 4
+TS_FLAG_INV_U16 = 8
 SCHED = {"auto": 0, "split": 1, "thm2": 2, "bitonic": 3, "merge": 4, "naive": 15}
 TS_OP_SORT, TS_OP_PARTITION, TS_OP_PERMUTE = 0, 1, 2
 

@@ -21,7 +21,9 @@ from . import ops
 class Permute(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, pi, offsets, max_tile_len=None):
-        inv = torch.empty_like(pi)
+        # the inverse is kept as 16-bit tile-local indices (every supported tile
+        # length fits), so the backward reads 2 bytes per element for it
+        inv = torch.empty(pi.shape, dtype=torch.int16, device=pi.device)
         y = ops.tile_permute(x.contiguous(), pi, "scatter", offsets, max_tile_len, inv_out=inv)
         ctx.save_for_backward(inv, offsets)
         ctx.max_tile_len = max_tile_len

@@ -288,6 +288,9 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int
     if (max_tile_len > ts::permute_split_capacity())
         return fail(TS_ERR_UNSUPPORTED, "tile_permute: max_tile_len %lld > %lld",
                     (long long)max_tile_len, (long long)ts::permute_split_capacity());
+    // the kernels address one tile of a payload channel through a 32-bit byte range
+    if (channels > 0 && (uint64_t)max_tile_len * (uint64_t)elem_stride * 4u >= (1ull << 32))
+        return fail(TS_ERR_UNSUPPORTED, "tile_permute: max_tile_len x elem_stride too large");
     ts::PermuteArgs a{};
     a.pay = ts::PayloadRef{in, out, channels, elem_stride, chan_stride};
     a.pi = pi;
@@ -296,6 +299,8 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int
     a.offsets = tile_offsets;
     a.num_tiles = num_tiles;
     a.validate = (flags & TS_FLAG_VALIDATE) ? 1u : 0u;
+    a.pi16 = (flags & TS_FLAG_PI_U16) ? 1u : 0u;
+    a.inv16 = (flags & TS_FLAG_INV_U16) ? 1u : 0u;
     a.err = (uint32_t*)workspace;
     hipStream_t s = (hipStream_t)stream;
     const int sched = sched_of(flags);
@@ -402,8 +407,8 @@ ts_status ts_tune(const char* knob, int value) {
         return TS_OK;
     }
     if (std::strcmp(knob, "permute_variant") == 0) {
-        if (!(value == 0 || value == 1 || value == 2 || value == 6 || value == 7 || value == 8))
-            return fail(TS_ERR_INVALID, "ts_tune: permute_variant must be one of 0, 1, 2, 6, 7, 8");
+        if (!(value == 0 || value == 1 || value == 2 || (value >= 6 && value <= 10)))
+            return fail(TS_ERR_INVALID, "ts_tune: permute_variant must be one of 0, 1, 2, 6, 7, 8, 9, 10");
         ts::set_permute_variant(value);
         return TS_OK;
     }

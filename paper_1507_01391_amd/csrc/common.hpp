@@ -39,6 +39,18 @@ TS_DEV uint32_t opaque(uint32_t v) {
     return v;
 }
 
+// The same for a wave-uniform value (kept in a scalar register): values derived from
+// it are recomputed with scalar instructions where they are used instead of being
+// hoisted, which can run out of scalar registers and spill them to vector lanes.
+TS_DEV int opaque_s(int v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+TS_DEV int64_t opaque_s64(int64_t v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 // Cross-lane exchange through LDS inside one wavefront.  The LDS executes a
 // wavefront's instructions in order, so no hardware wait is needed; what must be
 // stopped is the compiler moving loads and stores across this point: it reasons per
@@ -108,6 +120,51 @@ TS_DEV void load_columns(const T* __restrict__ base, int64_t stride, int64_t o, 
     }
 }
 
+// Buffer resource over `bytes` bytes from `base` (raw addressing, 4-byte granules):
+// loads at offsets past the end return 0 and stores there are dropped by the
+// hardware range check, so the edge of a tile needs no per-lane masks or fallback
+// addresses.  Every access below takes a byte offset; column j of a wave is the
+// per-lane offset plus an immediate.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+TS_DEV rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// CPW columns of 32-bit words: out[j] = word at byte lane_off + 256 j (0 past the end).
+template <int CPW, bool NT = false>
+TS_DEV void buffer_load_columns(rsrc_t r, uint32_t lane_off, uint32_t (&out)[CPW]) {
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+        out[j] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(lane_off + 256u * j), 0, NT ? 2 : 0);
+}
+
+// The same with a run-time column stride in bytes (elements `stride` words apart).
+template <int CPW, bool NT = false>
+TS_DEV void buffer_load_columns_strided(rsrc_t r, uint32_t lane_off, uint32_t col_bytes, uint32_t (&out)[CPW]) {
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+        out[j] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(lane_off + col_bytes * j), 0, NT ? 2 : 0);
+}
+
+// CPW columns of 16-bit values: out[j] = value at byte lane_off + 128 j (0 past the end).
+template <int CPW, bool NT = false>
+TS_DEV void buffer_load_columns16(rsrc_t r, uint32_t lane_off, uint32_t (&out)[CPW]) {
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+        out[j] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)(lane_off + 128u * j), 0, NT ? 2 : 0);
+}
+
+template <bool NT = false>
+TS_DEV void buffer_store(rsrc_t r, uint32_t byte_off, uint32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)byte_off, 0, NT ? 2 : 0);
+}
+
+template <bool NT = false>
+TS_DEV void buffer_store16(rsrc_t r, uint32_t byte_off, uint32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)byte_off, 0, NT ? 2 : 0);
+}
+
 // Store element g = 64*c + lane of a tile (g < n) at base[(o + g) * stride]; NT: a
 // streaming (nontemporal) store.
 template <bool NT = false, typename T>
@@ -135,6 +192,16 @@ TS_DEV uint64_t lds_load_u64_whole(const T* base, uint32_t byte_off) {
     uint64_t v = *(const uint64_t*)((const char*)base + byte_off);
     asm volatile("" : "+v"(v));
     return v;
+}
+
+// CPW 64-bit LDS loads issued back to back, then kept whole (see lds_load_u64_whole)
+// all together, so their latencies overlap.
+template <int CPW, typename T>
+TS_DEV void lds_load_columns_whole(const T* base, uint32_t byte_off, uint32_t col_bytes, uint64_t (&out)[CPW]) {
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) out[j] = *(const uint64_t*)((const char*)base + byte_off + col_bytes * j);
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) asm volatile("" : "+v"(out[j]));
 }
 
 TS_DEV uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }

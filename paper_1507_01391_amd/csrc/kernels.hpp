@@ -44,6 +44,8 @@ struct PermuteArgs {
     const int64_t* offsets;
     int64_t num_tiles;
     uint32_t validate;
+    uint32_t pi16;      // pi holds uint16 values
+    uint32_t inv16;     // inv_out receives uint16 values
     uint32_t* err;
 };
 

@@ -162,14 +162,24 @@ __global__ __launch_bounds__(NW * 64) void permute_naive_kernel(PermuteArgs a) {
         }
         const int n = (int)len;
         int32_t pidx[CPW];
-        load_columns<CPW>(a.pi, 1, o, n, w * CPW, lane, pidx, a.offsets);
+        if (a.pi16) {
+            uint16_t p16[CPW];
+            load_columns<CPW>((const uint16_t*)a.pi, 1, o, n, w * CPW, lane, p16, a.offsets);
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) pidx[j] = (int32_t)p16[j];
+        } else {
+            load_columns<CPW>(a.pi, 1, o, n, w * CPW, lane, pidx, a.offsets);
+        }
 #pragma unroll
         for (int j = 0; j < CPW; ++j) pidx[j] &= (CAP - 1);
         if (a.inv_out) {  // inv[pi[i]] = i, a direct scatter to global memory
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
                 const int i = 64 * (w * CPW + j) + lane;
-                if (i < n) a.inv_out[o + pidx[j]] = i;
+                if (i < n) {
+                    if (a.inv16) ((uint16_t*)a.inv_out)[o + pidx[j]] = (uint16_t)i;
+                    else a.inv_out[o + pidx[j]] = i;
+                }
             }
         }
         for (uint32_t c = 0; c < a.pay.channels; ++c) {

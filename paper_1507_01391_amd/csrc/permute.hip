@@ -6,10 +6,9 @@
 //            leaves inv[q] (the output slot that wants in[q]) at every slot q; then
 //            (in[q], destination inv[q]) is routed.  The first routing is shared by
 //            all payload channels.
-// Items carry the source index beside the destination (destination in the low 16
-// bits of the high word, source in the high 16), so either direction can also write
-// the inverse permutation at no extra routing: a scatter's caller can then undo it
-// with another scatter instead of a two-routing gather.
+// Item keys carry the source index beside the destination (route_key), so either
+// direction can also write the inverse permutation at no extra routing: a scatter's
+// caller can then undo it with another scatter instead of a two-routing gather.
 #include <algorithm>
 #include <cstdint>
 #include <type_traits>
@@ -24,6 +23,11 @@ namespace {
 
 // REPLAY (for two or more payload channels): channel 0 is routed and recorded, the
 // other channels replay the record two per 64-bit item.
+//
+// Global accesses go through buffer resources over the tile (pi, inv_out, and each
+// payload channel when its elements are contiguous): lanes past the end of the tile
+// read 0 and their stores are dropped by the hardware range check, so no per-lane
+// bounds test or address select is spent on them.
 template <int NW, int CAP, bool GATHER, int WPE, bool REPLAY, bool NT>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
 void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
@@ -33,12 +37,16 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
     __shared__ int wz[NW];
     __shared__ typename std::conditional<REPLAY, typename R::Plan, int>::type plan;
     const int lane0 = lane_id();
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr bool gather = GATHER;
+    const bool with_pay = a.pay.channels > 0;
+    const bool unit = a.pay.es == 1;  // channel words contiguous: buffer accesses
 
     for (int64_t t = blockIdx.x; t < a.num_tiles; t += gridDim.x) {
+        // lane- and wave-derived values are recomputed per tile instead of being hoisted
+        // out of the tile loop (and spilled)
         const int lane = (int)opaque((uint32_t)lane0);
-        const uint32_t own_base = (uint32_t)lane * 8u + (uint32_t)(w * CPW * 512);
+        const int w = opaque_s(w0);
         const int64_t o = offs[t];
         const int64_t len = offs[t + 1] - o;
         if (len > CAP) {
@@ -46,22 +54,73 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
             continue;
         }
         const int n = (int)len;
+        const uint32_t nb = (uint32_t)(n > 0 ? n : 0);
+        // byte offset of item 64 (w*CPW) + lane in 32-bit and 16-bit arrays; column j
+        // adds 256 j / 128 j
+        const uint32_t off32 = ((uint32_t)(64 * w * CPW) + (uint32_t)lane) * 4u;
+        const uint32_t off16 = off32 >> 1;
+        const rsrc_t rpi = a.pi16 ? buffer_rsrc((const uint16_t*)a.pi + o, nb * 2u)
+                                  : buffer_rsrc(a.pi + o, nb * 4u);
+        // resources of the outputs are built where they are used (from opaque copies of
+        // the tile offset), not kept in scalar registers across the routing
+        // payload channel c: words (o + g) * es + c * cs; a buffer over the tile's
+        // n * es words (the host keeps that below 2^32 bytes)
+        const uint32_t es = (uint32_t)a.pay.es;
+        auto pay_rsrc = [&](const uint32_t* base, uint32_t c) {
+            return buffer_rsrc(base + (int64_t)c * a.pay.cs + opaque_s64(o) * (int64_t)es, nb * es * 4u);
+        };
+        // lane offsets are passed in from an opaque copy of the lane taken where the
+        // access happens, so the compiler neither keeps per-column offsets live across a
+        // routing nor shares them with values computed before it
+        auto load_pay = [&](uint32_t c, uint32_t lane_off, uint32_t (&xv)[CPW]) {
+            const rsrc_t r = pay_rsrc(a.pay.in, c);
+            if (unit) buffer_load_columns<CPW, NT>(r, lane_off, xv);
+            else buffer_load_columns_strided<CPW, NT>(r, lane_off * es, 256u * es, xv);
+        };
+        // stores of whole columns, one uniform branch per call: lo32 (hi = false) or
+        // hi32 (hi = true) of x[j] to payload channel c; index values v[j] to inv_out
+        auto store_pay = [&](uint32_t c, uint32_t lane_off, const uint64_t (&x)[CPW], bool hi) {
+            const rsrc_t r = pay_rsrc(a.pay.out, c);
+            if (unit) {
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) buffer_store<NT>(r, lane_off + 256u * j, hi ? hi32(x[j]) : lo32(x[j]));
+            } else {
+#pragma unroll
+                for (int j = 0; j < CPW; ++j)
+                    buffer_store<NT>(r, lane_off * es + 256u * es * j, hi ? hi32(x[j]) : lo32(x[j]));
+            }
+        };
+        auto store_inv_cols = [&](uint32_t lane_off, const uint32_t (&v)[CPW]) {
+            const int64_t oo = opaque_s64(o);
+            if (a.inv16) {
+                const rsrc_t r = buffer_rsrc((uint16_t*)a.inv_out + oo, nb * 2u);
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) buffer_store16<NT>(r, (lane_off >> 1) + 128u * j, v[j]);
+            } else {
+                const rsrc_t r = buffer_rsrc(a.inv_out + oo, nb * 4u);
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) buffer_store<NT>(r, lane_off + 256u * j, v[j]);
+            }
+        };
+        auto lane_off_at = [&](int l) { return ((uint32_t)(64 * w * CPW) + (uint32_t)l) * 4u; };
 
         // ---- destinations: item i (column k, lane l; i = 64k + l) goes to pi[i];
         //      padding items i >= n keep their own index, so the destinations always
         //      form a permutation of [0, CAP).
         uint32_t dst[CPW];
-        bool bad = false;
-        int32_t piv[CPW];
-        load_columns<CPW, NT>(a.pi, 1, o, n, w * CPW, lane, piv, offs);
+        {
+            uint32_t piv[CPW];
+            if (a.pi16) buffer_load_columns16<CPW, NT>(rpi, off16, piv);
+            else buffer_load_columns<CPW, NT>(rpi, off32, piv);
+            bool bad = false;
 #pragma unroll
-        for (int j = 0; j < CPW; ++j) {
-            const int i = 64 * (w * CPW + j) + lane;
-            const int32_t q = piv[j];
-            bad |= (i < n) && (q < 0 || q >= n);
-            dst[j] = (i < n) ? ((uint32_t)q & (uint32_t)(CAP - 1)) : (uint32_t)i;
+            for (int j = 0; j < CPW; ++j) {
+                const int i = 64 * (w * CPW + j) + lane;
+                if (a.validate) bad |= (i < n) && (piv[j] >= (uint32_t)n);  // also catches q < 0
+                dst[j] = (i < n) ? (piv[j] & (uint32_t)(CAP - 1)) : (uint32_t)i;
+            }
+            if (a.validate) flag_error(a.err, bad, ERR_BAD_PERM);
         }
-        if (a.validate) flag_error(a.err, bad, ERR_BAD_PERM);
 
         uint64_t e[CPW];
         if (gather) {
@@ -69,22 +128,27 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
                 const int i = 64 * (w * CPW + j) + lane;
-                e[j] = pack(dst[j], (uint32_t)i);
+                e[j] = pack(route_key(dst[j], 0u), (uint32_t)i);
             }
             R::route(A, wz, e, w, lane);
+            const int lg = (int)opaque((uint32_t)lane);
+            lds_load_columns_whole<CPW>(A, (uint32_t)lg * 8u + (uint32_t)(w * CPW * 512), 512u, e);
+            if (a.validate) {
+                bool bad = false;
 #pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-                const int q = 64 * (w * CPW + j) + lane;
-                const uint64_t x = lds_load_u64_whole(A, own_base + 512u * j);
-                if (a.validate) flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)q, ERR_BAD_PERM);
-                dst[j] = lo32(x);  // inv[q] for q = 64k + l
-                if (a.inv_out && q < n) store_item<NT>(a.inv_out, 1, o, q, (int32_t)dst[j]);
+                for (int j = 0; j < CPW; ++j) bad |= key_dst(hi32(e[j])) != (uint32_t)(64 * (w * CPW + j) + lg);
+                flag_error(a.err, bad, ERR_BAD_PERM);
             }
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) dst[j] = lo32(e[j]);  // inv[q] for q = 64k + l
+            if (a.inv_out) store_inv_cols(lane_off_at(lg), dst);
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) dst[j] = route_key(dst[j], 0u);
             __syncthreads();  // A is reused by the next routing
         } else {
-            // the source index rides above the destination (for inv_out)
+            // the source index rides in the key (for inv_out)
 #pragma unroll
-            for (int j = 0; j < CPW; ++j) dst[j] |= (uint32_t)(64 * (w * CPW + j) + lane) << 16;
+            for (int j = 0; j < CPW; ++j) dst[j] = route_key(dst[j], (uint32_t)(64 * (w * CPW + j) + lane));
         }
 
         // a scatter asked only for the inverse still routes once (with no payload);
@@ -94,29 +158,30 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
         uint32_t pdst[REPLAY ? CPW : 1];
 #pragma unroll 1
         for (uint32_t c = 0; c < nroute; ++c) {
-            // per-column addresses are recomputed per channel instead of being kept
-            // live (or spilled) across the whole channel loop
             const int lc = (int)opaque((uint32_t)lane);
-            const uint32_t own_c = (uint32_t)lc * 8u + (uint32_t)(w * CPW * 512);
-            const int64_t cbase = (int64_t)c * a.pay.cs;
-            const bool with_pay = a.pay.channels > 0;
             uint32_t xv[CPW];
-            load_columns<CPW, NT>(a.pay.in + (with_pay ? cbase : 0), a.pay.es, o, with_pay ? n : 0, w * CPW,
-                              lc, xv, offs);
+            if (with_pay) load_pay(c, lane_off_at(lc), xv);
+            else
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) xv[j] = 0u;
 #pragma unroll
             for (int j = 0; j < CPW; ++j) e[j] = pack(dst[j], xv[j]);
             if constexpr (REPLAY) R::template route<true>(A, wz, e, w, lane, &plan, pdst);
             else R::route(A, wz, e, w, lane);
+            const int ls = (int)opaque((uint32_t)lane);
+            lds_load_columns_whole<CPW>(A, (uint32_t)ls * 8u + (uint32_t)(w * CPW * 512), 512u, e);
+            if (a.validate && c == 0 && !gather) {
+                bool bad = false;
 #pragma unroll
-            for (int j = 0; j < CPW; ++j) {
-                const int v = 64 * (w * CPW + j) + lc;
-                const uint64_t x = lds_load_u64_whole(A, own_c + 512u * j);
-                if (a.validate && c == 0 && !gather)
-                    flag_error(a.err, (hi32(x) & (CAP - 1)) != (uint32_t)v, ERR_BAD_PERM);
-                if (v < n) {
-                    if (with_pay) store_item<NT>(a.pay.out + cbase, a.pay.es, o, v, lo32(x));
-                    if (!gather && c == 0 && a.inv_out) store_item<NT>(a.inv_out, 1, o, v, (int32_t)(hi32(x) >> 16));
-                }
+                for (int j = 0; j < CPW; ++j) bad |= key_dst(hi32(e[j])) != (uint32_t)(64 * (w * CPW + j) + ls);
+                flag_error(a.err, bad, ERR_BAD_PERM);
+            }
+            if (with_pay) store_pay(c, lane_off_at(ls), e, false);
+            if (!gather && c == 0 && a.inv_out) {
+                uint32_t src[CPW];
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) src[j] = key_src(hi32(e[j]));
+                store_inv_cols(lane_off_at(ls), src);
             }
             __syncthreads();  // A is reused by the next channel / tile
         }
@@ -124,25 +189,17 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
 #pragma unroll 1
             for (uint32_t c = 1; c < a.pay.channels; c += 2) {
                 const int lc = (int)opaque((uint32_t)lane);
-                const uint32_t own_c = (uint32_t)lc * 8u + (uint32_t)(w * CPW * 512);
                 const bool two = c + 1 < a.pay.channels;
-                const int64_t cb0 = (int64_t)c * a.pay.cs;
-                const int64_t cb1 = two ? cb0 + a.pay.cs : cb0;
                 uint32_t x0[CPW], x1[CPW];
-                load_columns<CPW, NT>(a.pay.in + cb0, a.pay.es, o, n, w * CPW, lc, x0, offs);
-                load_columns<CPW, NT>(a.pay.in + cb1, a.pay.es, o, n, w * CPW, lc, x1, offs);
+                load_pay(c, lane_off_at(lc), x0);
+                load_pay(two ? c + 1 : c, lane_off_at(lc), x1);
 #pragma unroll
                 for (int j = 0; j < CPW; ++j) e[j] = pack(x1[j], x0[j]);
                 R::replay(A, &plan, e, pdst, w, lane);
-#pragma unroll
-                for (int j = 0; j < CPW; ++j) {
-                    const int v = 64 * (w * CPW + j) + lc;
-                    const uint64_t x = lds_load_u64_whole(A, own_c + 512u * j);
-                    if (v < n) {
-                        store_item<NT>(a.pay.out + cb0, a.pay.es, o, v, lo32(x));
-                        if (two) store_item<NT>(a.pay.out + cb1, a.pay.es, o, v, hi32(x));
-                    }
-                }
+                const int ls = (int)opaque((uint32_t)lane);
+                lds_load_columns_whole<CPW>(A, (uint32_t)ls * 8u + (uint32_t)(w * CPW * 512), 512u, e);
+                store_pay(c, lane_off_at(ls), e, false);
+                if (two) store_pay(c + 1, lane_off_at(ls), e, true);
                 __syncthreads();  // A is reused by the next pair / tile
             }
         }

@@ -18,9 +18,13 @@
 //     (t + l) mod m of group l (a skewed, conflict-free read) and writes it to
 //     its destination slot, which lies in bank l: every lane writes its own bank.
 //
-// Items carry the destination in the low 16 bits of their high word.  The tile
-// is padded to the capacity; padding items must carry the unused destinations
-// so that every bank still receives exactly N/64 items.
+// The high word of an item is its key: the destination bank (dst mod 64) in bits
+// 31..26, the slot inside the bank (dst / 64) in bits 25..18 and a 14-bit source index
+// in bits 13..0.  With the bank bits on top, all items of a level-L segment share the
+// key's top L bits (the segment index), so the bank bit split at that level is one
+// unsigned comparison against a per-segment threshold.  The tile is padded to the
+// capacity; padding items must carry the unused destinations so that every bank still
+// receives exactly N/64 items.
 //
 // A routing can be recorded (every column's ballot at every level, the zeros before
 // each wave at the levels whose segments span waves, and every item's placement slot)
@@ -33,13 +37,23 @@
 
 namespace ts {
 
+// Key of an item bound for slot dst (< 16384) with source index src (< 16384).
+TS_DEV uint32_t route_key(uint32_t dst, uint32_t src) {
+    return ((dst & 63u) << 26) | ((dst >> 6) << 18) | src;
+}
+TS_DEV uint32_t key_dst(uint32_t key) { return (((key >> 18) & 0xFFu) << 6) | (key >> 26); }
+TS_DEV uint32_t key_src(uint32_t key) { return key & 0x3FFFu; }
+
 template <int NW, int CAP>
 struct Router {
     static constexpr int NCOL = CAP / 64;   // columns of the tile
     static constexpr int CPW = NCOL / NW;   // columns per wave
     static constexpr int M = CAP / 64;      // items per bank
+    static constexpr int LOG_NCOL = __builtin_ctz(NCOL);
     static_assert(CPW * NW == NCOL, "capacity must split evenly over the waves");
     static_assert(M >= 64, "tiles of at least 64 x 64 items");
+    static_assert(CAP <= 16384, "keys hold 14-bit slots and sources");
+    static constexpr int KEEP_MAX = 8;      // above this, ballots are recomputed (scalar registers)
 
     // Record of one routing (lives in LDS next to A).
     struct Plan {
@@ -55,11 +69,11 @@ struct Router {
     // column and r0 the zeros in lower lanes; i.e. to seg_base + z + r0 +
     // (one ? 64 (seg_cols - k_in) - 1 - lane : 0), the bracket folded into the rank count.
     template <int L, int MODE>
-    static TS_DEV void split_level(uint64_t* A, int* wz, uint64_t (&e)[CPW], int w, int lane, Plan* plan) {
-        constexpr int bit = 5 - L;                 // bank bit split at this level
+    static TS_DEV void split_level(uint64_t* A, int* wz, uint64_t (&e)[CPW], int w_in, int lane, Plan* plan) {
+        const int w = opaque_s(w_in);              // per-level column constants stay local
         constexpr int seg_cols = NCOL >> L;        // columns per segment
         constexpr bool shared = seg_cols > CPW;    // segment spans several waves
-        constexpr bool keep = CPW <= 8;            // zero masks kept between the two loops
+        constexpr bool keep = CPW <= KEEP_MAX;     // zero masks kept between the two loops
         const uint32_t lane8 = opaque((uint32_t)lane * 8u);
         const uint32_t own_base = lane8 + (uint32_t)(w * CPW * 512);  // column j at + 512 j
         auto zero_mask = [&](int j) -> uint64_t {
@@ -69,7 +83,10 @@ struct Router {
                 return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(hi32(bv)) << 32) |
                        (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(lo32(bv));
             } else {
-                return ballot(((hi32(e[j]) >> bit) & 1u) == 0u);
+                // segment index = the key's top L bits; the split bit follows them
+                const uint32_t seg = (uint32_t)((w * CPW + j) >> (LOG_NCOL - L));
+                const uint32_t thr = (L == 0 ? 0u : (seg << ((32 - L) & 31))) | (1u << (31 - L));
+                return ballot(hi32(e[j]) < thr);
             }
         };
         uint64_t zm[keep ? CPW : 1];
@@ -154,7 +171,7 @@ struct Router {
         gather_groups(A, e, w, lane);
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
-            const uint32_t dst = hi32(e[j]) & (uint32_t)(CAP - 1);
+            const uint32_t dst = key_dst(hi32(e[j]));
             if (RECORD) pdst[j] = dst;
             lds_store(A, dst * 8u, e[j]);
         }

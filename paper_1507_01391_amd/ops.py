@@ -134,9 +134,10 @@ def tile_permute(x: Optional[torch.Tensor], pi: torch.Tensor, direction: str = "
                  validate: bool = False, out: Optional[torch.Tensor] = None,
                  inv_out: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
     """Apply tile-local permutations: scatter out[pi[i]] = x[i], gather out[i] = x[pi[i]].
-    ``x`` is [N] or [C, N] (channel-planar), or None when only ``inv_out`` (int32 [N],
-    receives inv_out[pi[i]] = i from the same routing) is wanted.  Returns ``out``."""
-    assert pi.dtype == torch.int32 and pi.is_cuda
+    ``x`` is [N] or [C, N] (channel-planar), or None when only ``inv_out`` (receives
+    inv_out[pi[i]] = i from the same routing) is wanted.  ``pi`` and ``inv_out`` are
+    int32, or int16 holding the 16-bit tile-local indices.  Returns ``out``."""
+    assert pi.dtype in (torch.int32, torch.int16) and pi.is_cuda and pi.is_contiguous()
     n = pi.shape[0]
     dev = pi.device
     if x is not None:
@@ -145,12 +146,16 @@ def tile_permute(x: Optional[torch.Tensor], pi: torch.Tensor, direction: str = "
         if out is None:
             out = torch.empty_like(x)
     if inv_out is not None:
-        assert inv_out.dtype == torch.int32 and inv_out.shape[0] == n and inv_out.is_contiguous()
+        assert inv_out.dtype in (torch.int32, torch.int16) and inv_out.shape[0] == n and inv_out.is_contiguous()
     off = _offsets(offsets, n, dev)
     ch, es, cs = _payload_layout(x, n)
     d = {"scatter": _lib.TS_SCATTER, "gather": _lib.TS_GATHER}[direction]
     ws = workspace(dev)
     flags = _lib.sched_flags(schedule) | (_lib.TS_FLAG_VALIDATE if validate else 0)
+    if pi.dtype == torch.int16:
+        flags |= _lib.TS_FLAG_PI_U16
+    if inv_out is not None and inv_out.dtype == torch.int16:
+        flags |= _lib.TS_FLAG_INV_U16
     lib = _lib.load()
     _lib.check(lib.tile_permute(_ptr(x), _ptr(out), ch, es, cs, _ptr(pi), d, _ptr(inv_out),
                                 _ptr(off), off.numel() - 1, _max_len(off, max_tile_len), flags,

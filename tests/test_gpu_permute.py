@@ -80,7 +80,7 @@ def test_validate_reports_non_permutation(ts, direction):
         ts.check_device_errors()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8])
+@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8, 9, 10])
 @pytest.mark.parametrize("direction", ["scatter", "gather"])
 def test_permute_variants(ts, oracle, variant, direction):
     x, pi, _, off = inputs.permutation(seed=43, num_tiles=24, n=8192, family="uniform")
@@ -148,7 +148,7 @@ def test_multichannel_replay(ts, oracle, channels, direction, cap):
     run_and_compare(ts, oracle, x, pi, off, direction, max_len=cap)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8])
+@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8, 9, 10])
 def test_multichannel_replay_variants(ts, oracle, variant):
     x, pi, _, off = inputs.permutation(seed=72, num_tiles=12, n=8192, family="transpose")
     x4 = np.stack([x, -x, 2 * x, x + 1]).astype(np.float32)
@@ -159,3 +159,34 @@ def test_multichannel_replay_variants(ts, oracle, variant):
             run_and_compare(ts, oracle, x4, pi, off, direction, max_len=8192)
     finally:
         ts.tune("permute_variant", prev)
+
+
+@pytest.mark.parametrize("schedule", ["split", "naive"])
+@pytest.mark.parametrize("direction", ["scatter", "gather"])
+@pytest.mark.parametrize("cap", [4096, 16384])
+def test_16bit_indices(ts, oracle, schedule, direction, cap):
+    """pi read as uint16 (TS_FLAG_PI_U16) and the inverse written as uint16
+    (TS_FLAG_INV_U16): same outputs as with int32 indices."""
+    import torch
+    from tests.gpu_util import dev, host_u32
+    rng = np.random.default_rng(cap + 3 * (direction == "gather"))
+    sizes = np.array([cap, 0, 1, 65, cap - 1, cap // 3])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pi = np.concatenate([rng.permutation(int(s)) for s in sizes]).astype(np.int32)
+    x = rng.standard_normal((3, off[-1])).astype(np.float32)
+    pi16 = torch.from_numpy(pi.astype(np.int16)).cuda()
+    inv16 = torch.full((off[-1],), -7, dtype=torch.int16, device="cuda")
+    out = ts.tile_permute(dev(x), pi16, direction, dev(off), max_tile_len=cap, schedule=schedule,
+                          inv_out=inv16)
+    ts.check_device_errors()
+    d = oracle.SCATTER if direction == "scatter" else oracle.GATHER
+    want = oracle.tile_permute(x.view(np.uint32), pi, d, off, nthreads=8)
+    assert np.array_equal(host_u32(out).reshape(want.shape), want)
+    got_inv = inv16.cpu().numpy().astype(np.int32) & 0xFFFF
+    assert np.array_equal(got_inv, inverse_reference(pi, off))
+    # the backward of a scatter: a scatter by the 16-bit inverse equals the gather by pi
+    if direction == "scatter":
+        g = rng.standard_normal(off[-1]).astype(np.float32)
+        gx = ts.tile_permute(dev(g), inv16, "scatter", dev(off), max_tile_len=cap, schedule=schedule)
+        want_g = oracle.tile_permute(g.view(np.uint32), pi, oracle.GATHER, off, nthreads=8)
+        assert np.array_equal(host_u32(gx), want_g)
