@@ -239,6 +239,9 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
     if (max_tile_len > ts::partition_split_capacity())
         return fail(TS_ERR_UNSUPPORTED, "tile_partition: max_tile_len %lld > %lld",
                     (long long)max_tile_len, (long long)ts::partition_split_capacity());
+    // the kernels address one tile of the payload through a 32-bit byte range
+    if (channels > 0 && (uint64_t)max_tile_len * (uint64_t)elem_stride * 4u >= (1ull << 32))
+        return fail(TS_ERR_UNSUPPORTED, "tile_partition: max_tile_len x elem_stride too large");
     ts::PartitionArgs a{};
     a.labels_in = labels_in;
     a.labels_out = labels_out;

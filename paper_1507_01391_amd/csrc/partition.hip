@@ -62,22 +62,27 @@ struct TileLoad {
     uint32_t pay[CPW];
 };
 
-// Issue the global loads of one tile (no waits).  Lanes past the end read item 0 of
-// the tile (always valid when n > 0) and are replaced by padding later.
+// Issue the global loads of one tile (no waits) through buffer resources over the
+// tile: lanes past the end read 0 (the hardware range check) and are replaced by
+// padding later.
 template <int CPW, int CAP, bool NT = false>
 TS_DEV void issue_tile_load(const SplitArgs& a, const int64_t* __restrict__ offs, int64_t t,
                             int w, int lane, TileLoad<CPW>& L) {
-    // Branch-free: an absent tile reads the offsets of tile 0 and loads nothing useful,
-    // so the previous contents of L never have to be kept alive.
+    // Branch-free: an absent tile reads the offsets of tile 0 and loads nothing, so the
+    // previous contents of L never have to be kept alive.
     const bool exists = t < a.num_tiles;
     const int64_t tt = exists ? t : 0;
     const int64_t o = offs[tt];
     const int64_t len = offs[tt + 1] - o;
     L.o = o;
     L.n = !exists ? -1 : ((len > CAP) ? -2 : (int)len);
-    const int nn = (L.n > 0) ? L.n : 0;
-    load_columns<CPW, NT>(a.keys_in, 1, o, nn, w * CPW, lane, L.lab, offs);
-    load_columns<CPW, NT>(a.pay_in, a.pay_es, o, a.has_pay ? nn : 0, w * CPW, lane, L.pay, offs);
+    const uint32_t nn = (uint32_t)((L.n > 0) ? L.n : 0);
+    const uint32_t off = ((uint32_t)(64 * w * CPW) + (uint32_t)lane) * 4u;
+    buffer_load_columns<CPW, NT>(buffer_rsrc(a.keys_in + o, nn * 4u), off, L.lab);
+    const uint32_t es = (uint32_t)a.pay_es;
+    const rsrc_t rp = buffer_rsrc(a.pay_in + o * (int64_t)es, a.has_pay ? nn * es * 4u : 0u);
+    if (es == 1) buffer_load_columns<CPW, NT>(rp, off, L.pay);
+    else buffer_load_columns_strided<CPW, NT>(rp, off * es, 256u * es, L.pay);
 }
 
 template <int NW, int CAP, int WPE, int MODE, int PF = -1, int NTM = 0>
@@ -92,18 +97,19 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
     __shared__ uint64_t A[CAP];
     __shared__ int wz[NW];
     const int lane0 = lane_id();
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint32_t lmask = (MODE == 0) ? (1u << a.nbits) - 1u : 0xFFFFFFFFu;
     const bool has_pay = a.has_pay != 0;
 
     TileLoad<CPW> L;
     int64_t t = blockIdx.x;
-    issue_tile_load<CPW, CAP, NTL>(a, offs, t, w, lane0, L);
+    issue_tile_load<CPW, CAP, NTL>(a, offs, t, w0, lane0, L);
 
     for (; t < a.num_tiles; t += gridDim.x) {
         // lane-derived values (positions, addresses) are recomputed per tile rather
         // than hoisted out of the tile loop and kept live across it
         const int lane = (int)opaque((uint32_t)lane0);
+        const int w = opaque_s(w0);
         const int64_t o = L.o;
         const int n = L.n;
         if (n == -2) {  // longer than this kernel's capacity: skip and flag
@@ -207,20 +213,41 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
             }
         }
 
-        // ---- store in order (coalesced: column k covers items 64k .. 64k+63)
+        // ---- store in order (coalesced: column k covers items 64k .. 64k+63), one
+        //      uniform branch per output; stores past the end of the tile are dropped by
+        //      the buffer range check
+        {
+            const int ls = (int)opaque((uint32_t)lane);
+            const uint32_t off = ((uint32_t)(64 * w * CPW) + (uint32_t)ls) * 4u;
+            const uint32_t nb = (uint32_t)n * 4u;
+            uint32_t v[CPW];
+            if (a.keys_out) {
+                const rsrc_t r = buffer_rsrc(a.keys_out + o, nb);
 #pragma unroll
-        for (int j = 0; j < CPW; ++j) {
-            const int v = 64 * (w * CPW + j) + lane;
-            if (v < n) {
-                const uint32_t h = hi32(e[j]);
-                if (MODE == 0) {
-                    if (a.keys_out) store_item<NTS>(a.keys_out, 1, o, v, h & 0xFFFFu);
-                    if (has_pay) store_item<NTS>(a.pay_out, a.pay_es, o, v, lo32(e[j]));
-                    if (a.perm_out) store_item<NTS>(a.perm_out, 1, o, v, (int32_t)(h >> 16));
-                } else {
-                    if (a.keys_out) store_item<NTS>(a.keys_out, 1, o, v, a.f32 ? ordered_to_f32(h) : h);
-                    if (a.perm_out) store_item<NTS>(a.perm_out, 1, o, v, (int32_t)lo32(e[j]));
+                for (int j = 0; j < CPW; ++j) {
+                    const uint32_t h = hi32(e[j]);
+                    v[j] = (MODE == 0) ? (h & 0xFFFFu) : (a.f32 ? ordered_to_f32(h) : h);
                 }
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) buffer_store<NTS>(r, off + 256u * j, v[j]);
+            }
+            if (MODE == 0 && has_pay) {
+                const uint32_t es = (uint32_t)a.pay_es;
+                const rsrc_t r = buffer_rsrc(a.pay_out + o * (int64_t)es, nb * es);
+                if (es == 1) {
+#pragma unroll
+                    for (int j = 0; j < CPW; ++j) buffer_store<NTS>(r, off + 256u * j, lo32(e[j]));
+                } else {
+#pragma unroll
+                    for (int j = 0; j < CPW; ++j) buffer_store<NTS>(r, off * es + 256u * es * j, lo32(e[j]));
+                }
+            }
+            if (a.perm_out) {
+                const rsrc_t r = buffer_rsrc(a.perm_out + o, nb);
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) v[j] = (MODE == 0) ? (hi32(e[j]) >> 16) : lo32(e[j]);
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) buffer_store<NTS>(r, off + 256u * j, v[j]);
             }
         }
         if (!PREFETCH) issue_tile_load<CPW, CAP, NTL>(a, offs, t + gridDim.x, w, lane, L);
