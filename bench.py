@@ -37,7 +37,7 @@ PERMUTE_BYTES_PER_ELEM = 12
 MEASURED_TRAFFIC = {"bytes_per_launch": 4.3035e9, "tiles": 65536, "partition_waves_4096": 168,
                     "sources": ["paper_1507_01391_amd/csrc/partition.hip",
                                 "paper_1507_01391_amd/csrc/common.hpp"],
-                    "sha256_prefix": "0e63416115bc12fa"}
+                    "sha256_prefix": "c55a2b8c78f31379"}
 
 
 def sources_hash(paths):
@@ -225,7 +225,7 @@ def bench_c1(torch, ts, inputs):
     do = torch.from_numpy(off).cuda()
     ko, po, pm = torch.empty_like(dk), torch.empty_like(dp), torch.empty_like(dk)
     out = {}
-    for sched in ("bitonic", "merge", "naive"):
+    for sched in ("bitonic", "split", "merge", "naive"):
         _, m, _ = timed_launches(lambda: ts.tile_sort(dk, dp, do, max_tile_len=4096, schedule=sched,
                                                       keys_out=ko, payload_out=po, perm_out=pm),
                                  200, 20, torch)
@@ -268,9 +268,16 @@ def bench_c3(args, torch, ts, inputs):
         ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y, schedule="naive")
         ts.tile_permute(dg, dpi, "gather", doff, max_tile_len=8192, out=gx, schedule="naive")
 
-    for name, fn in (("split", split_fwd_bwd), ("split_inv32", split_fwd_bwd_inv32),
-                     ("split_scatter_plus_gather", split_scatter_gather),
-                     ("naive", naive_fwd_bwd), ("naive_oneshot", naive_fwd_bwd)):
+    variants = (("split", split_fwd_bwd), ("split_inv32", split_fwd_bwd_inv32),
+                ("split_scatter_plus_gather", split_scatter_gather),
+                ("naive", naive_fwd_bwd), ("naive_oneshot", naive_fwd_bwd))
+    # one untimed round over every variant first: the first timed loop of a process
+    # otherwise also pays for clocks ramping up
+    for _, fn in variants:
+        for _ in range(3):
+            fn()
+    torch.cuda.synchronize()
+    for name, fn in variants:
         ts.tune("naive_oneshot", 1 if name == "naive_oneshot" else 0)
         log(f"[bench] C3 fwd+bwd permute ({name}) ...")
         w, m, _ = timed_launches(fn, 10, 3, torch)
