@@ -112,14 +112,18 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
             uint32_t piv[CPW];
             if (a.pi16) buffer_load_columns16<CPW, NT>(rpi, off16, piv);
             else buffer_load_columns<CPW, NT>(rpi, off32, piv);
-            bool bad = false;
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
                 const int i = 64 * (w * CPW + j) + lane;
-                if (a.validate) bad |= (i < n) && (piv[j] >= (uint32_t)n);  // also catches q < 0
                 dst[j] = (i < n) ? (piv[j] & (uint32_t)(CAP - 1)) : (uint32_t)i;
             }
-            if (a.validate) flag_error(a.err, bad, ERR_BAD_PERM);
+            if (a.validate) {  // one branch for the whole check
+                bool bad = false;
+#pragma unroll
+                for (int j = 0; j < CPW; ++j)
+                    bad |= (64 * (w * CPW + j) + lane < n) && (piv[j] >= (uint32_t)n);  // also catches q < 0
+                flag_error(a.err, bad, ERR_BAD_PERM);
+            }
         }
 
         uint64_t e[CPW];
