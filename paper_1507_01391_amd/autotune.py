@@ -34,7 +34,7 @@ KNOBS = {
     "merge_pack": ([1, 0], 1),
     "oneshot": ([1, 0], 1),
     "partition_waves_4096": ([168, 176, 166, 164, 106, 108, 104], 168),
-    "permute_variant": ([6, 7, 8, 1, 0, 2], 6),
+    "permute_variant": ([6, 7, 8, 9, 1, 0, 2], 6),
 }
 
 
