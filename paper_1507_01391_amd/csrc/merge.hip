@@ -131,20 +131,28 @@ TS_DEV void store_final_regs(const SortArgs& s, int64_t o, int64_t rb, int nvali
                              const uint64_t (&v)[R], int c0, int lane, bool narrow) {
     const int ln = (int)opaque((uint32_t)lane);
     const PayloadRef& p = s.pay;
-    // keys and positions, addressed as one wave-uniform pointer plus 32-bit byte
-    // offsets; afterwards only the positions stay live
-    uint32_t* kb = s.keys_out ? s.keys_out + o + rb : nullptr;
-    int32_t* pb = s.perm_out ? s.perm_out + o + rb : nullptr;
+    const uint32_t nv = (uint32_t)(nvalid > 0 ? nvalid : 0);
+    const uint32_t off = (uint32_t)ln * 4u;  // byte offset of column 0; column c at + 256 c
+    // keys and positions through buffer resources over the piece's outputs: stores of
+    // ranks >= nvalid are dropped by the range check; afterwards only the positions stay
+    // live
     uint32_t pos_of[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const int q = 64 * c + ln;
-        const uint32_t key = comp_key(v[c0 + c]);
-        pos_of[c] = comp_pos(v[c0 + c]);
-        if (q < nvalid) {
-            if (kb) *(uint32_t*)((char*)kb + (uint32_t)q * 4u) = s.f32 ? ordered_to_f32(key) : key;
-            if (pb) *(int32_t*)((char*)pb + (uint32_t)q * 4u) = (int32_t)pos_of[c];
+    for (int c = 0; c < NC; ++c) pos_of[c] = comp_pos(v[c0 + c]);
+    if (s.keys_out) {
+        const rsrc_t r = buffer_rsrc(s.keys_out + o + rb, nv * 4u);
+        if (s.f32) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) buffer_store(r, off + 256u * c, ordered_to_f32(comp_key(v[c0 + c])));
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) buffer_store(r, off + 256u * c, comp_key(v[c0 + c]));
         }
+    }
+    if (s.perm_out) {
+        const rsrc_t r = buffer_rsrc(s.perm_out + o + rb, nv * 4u);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) buffer_store(r, off + 256u * c, pos_of[c]);
     }
     if (p.channels == 0) return;
     constexpr int G = NC < 16 ? NC : 16;
@@ -154,25 +162,37 @@ TS_DEV void store_final_regs(const SortArgs& s, int64_t o, int64_t rb, int nvali
         const uint32_t* pin = p.in + (int64_t)ch * p.cs + o * p.es;           // tile item 0
         uint32_t* pout = p.out + (int64_t)ch * p.cs + (o + rb) * p.es;        // rank rb
         const uint32_t es4 = (uint32_t)p.es * 4u;
+        if (narrow) {
+            // gather through the positions (the whole tile is addressable with 32-bit
+            // offsets), stores through a buffer over the piece's outputs
+            const rsrc_t rin = buffer_rsrc(pin, 0xFFFFFFFFu);
+            const rsrc_t rout = buffer_rsrc(pout, nv * es4);
+            const uint32_t loff = (uint32_t)lc * es4;
 #pragma unroll
-        for (int g = 0; g < NC; g += G) {
-            uint32_t pv[G];
+            for (int g = 0; g < NC; g += G) {
+                uint32_t pv[G];
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                const int q = 64 * (g + j) + lc;
-                if (narrow) {
-                    const uint32_t off = (q < nvalid) ? pos_of[g + j] * es4 : 0u;
-                    pv[j] = *(const uint32_t*)((const char*)pin + off);
-                } else {
+                for (int j = 0; j < G; ++j) {
+                    const int q = 64 * (g + j) + lc;
+                    const uint32_t src = (q < nvalid) ? pos_of[g + j] * es4 : 0u;
+                    pv[j] = __builtin_amdgcn_raw_buffer_load_b32(rin, (int)src, 0, 0);
+                }
+#pragma unroll
+                for (int j = 0; j < G; ++j) buffer_store(rout, loff + (uint32_t)(64 * (g + j)) * es4, pv[j]);
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < NC; g += G) {
+                uint32_t pv[G];
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    const int q = 64 * (g + j) + lc;
                     pv[j] = *((q < nvalid) ? pin + (int64_t)pos_of[g + j] * p.es : pin);
                 }
-            }
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                const int q = 64 * (g + j) + lc;
-                if (q < nvalid) {
-                    if (narrow) *(uint32_t*)((char*)pout + (uint32_t)q * es4) = pv[j];
-                    else pout[(int64_t)q * p.es] = pv[j];
+                for (int j = 0; j < G; ++j) {
+                    const int q = 64 * (g + j) + lc;
+                    if (q < nvalid) pout[(int64_t)q * p.es] = pv[j];
                 }
             }
         }
