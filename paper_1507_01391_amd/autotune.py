@@ -87,17 +87,26 @@ def _offsets(sizes: np.ndarray) -> np.ndarray:
     return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
 
 
-def _sort_bench(rng, lo: int, hi: int, keys_total: int, schedule_of: Callable[[int], str]):
-    tiles = max(64, keys_total // ((lo + hi) // 2))
-    off = _offsets(_sizes(rng, tiles, lo, hi))
+def _sort_bench(rng, lo: int, hi: int, keys_total: int, schedule_of: Callable[[int], str],
+                log_uniform: bool = False, payload: bool = False):
+    if log_uniform:   # segment lengths as in the uneven-segment workload
+        mean = (hi - lo) / np.log(hi / lo)
+        tiles = max(64, int(keys_total // mean))
+        sizes = np.exp(rng.uniform(np.log(lo), np.log(hi + 1), size=tiles)).astype(np.int64).clip(lo, hi)
+    else:
+        tiles = max(64, keys_total // ((lo + hi) // 2))
+        sizes = _sizes(rng, tiles, lo, hi)
+    off = _offsets(sizes)
     n = int(off[-1])
     keys = torch.from_numpy(rng.integers(0, 2**32, size=n, dtype=np.uint32).view(np.int32)).cuda()
+    pay = torch.arange(n, dtype=torch.int32, device="cuda") if payload else None
     d_off = torch.from_numpy(off).cuda()
     ko, pm = torch.empty_like(keys), torch.empty_like(keys)
+    po = torch.empty_like(keys) if payload else None
 
     def run(value: int):
-        return lambda: ops.tile_sort(keys, None, d_off, max_tile_len=hi, schedule=schedule_of(value),
-                                     keys_out=ko, perm_out=pm)
+        return lambda: ops.tile_sort(keys, pay, d_off, max_tile_len=hi, schedule=schedule_of(value),
+                                     keys_out=ko, payload_out=po, perm_out=pm)
     return run, n
 
 
@@ -133,8 +142,9 @@ def tune(quick: bool = False, log=print) -> dict:
         baseline[knob] = _time_ms(run(SORT["naive"]), reps)
         ops.tune(knob, plan[knob])
 
-    # packing of short tiles in the merge schedule
-    run, n = _sort_bench(rng, 256, 4096, total, lambda v: "merge")
+    # packing of short tiles in the merge schedule: log-uniform lengths with a payload,
+    # as in the uneven-segment workload
+    run, n = _sort_bench(rng, 256, 4096, total, lambda v: "merge", log_uniform=True, payload=True)
     choose("merge_pack", run, n, set_knob=True)
 
     # launch shape of the kernels without a variant table: a partition of 2048-item
