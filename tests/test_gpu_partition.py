@@ -119,3 +119,33 @@ def test_sort_schedules_payload_without_perm(ts, oracle, schedule):
     ts.check_device_errors()
     assert perm is None
     assert np.array_equal(host_u32(lo), want_l) and np.array_equal(host_u32(po), want_p)
+
+
+def test_strided_payload_through_c_abi(ts, oracle):
+    """One payload channel whose words are 3 apart (the first word of a 3-word struct),
+    through the C interface directly: the split kernel's strided buffer path."""
+    import ctypes
+    import torch
+    from paper_1507_01391_amd import _lib, ops
+    from tests.gpu_util import dev
+    rng = np.random.default_rng(91)
+    sizes = np.array([4096, 17, 0, 4000, 4096, 1])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    labels = rng.integers(0, 64, size=n, dtype=np.uint32)
+    structs = rng.integers(0, 2**32, size=(n, 3), dtype=np.uint32)
+    d_lab, d_st, d_off = dev(labels), dev(structs.ravel()), dev(off)
+    lab_out = torch.empty_like(d_lab)
+    st_out = torch.zeros_like(d_st)
+    lib = _lib.load()
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    ws = ops.workspace(d_lab.device, lib.ts_workspace_bytes(_lib.TS_OP_PARTITION, 0, len(sizes), n, 4096, 1))
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(lib.tile_partition(P(d_lab), P(lab_out), P(d_st), P(st_out), 1, 3, 0, 64, None, P(d_off),
+                                  len(sizes), 4096, _lib.sched_flags("split"), P(ws), ws.numel() * 4, stream))
+    ts.check_device_errors()
+    wl, wp, _ = oracle.tile_partition(labels, structs[:, 0].copy(), off, num_classes=64)
+    got = st_out.cpu().numpy().view(np.uint32).reshape(n, 3)
+    assert np.array_equal(lab_out.cpu().numpy().view(np.uint32), wl)
+    assert np.array_equal(got[:, 0], wp)
+    assert not got[:, 1:].any()          # the other words of each struct are untouched

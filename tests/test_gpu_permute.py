@@ -190,3 +190,23 @@ def test_16bit_indices(ts, oracle, schedule, direction, cap):
         gx = ts.tile_permute(dev(g), inv16, "scatter", dev(off), max_tile_len=cap, schedule=schedule)
         want_g = oracle.tile_permute(g.view(np.uint32), pi, oracle.GATHER, off, nthreads=8)
         assert np.array_equal(host_u32(gx), want_g)
+
+
+@pytest.mark.parametrize("direction", ["scatter", "gather"])
+@pytest.mark.parametrize("cap", [4096, 8192, 16384])
+def test_64bit_payload(ts, oracle, direction, cap):
+    """A float64 payload is moved as two 32-bit words per element (elem_stride 2,
+    chan_stride 1): the strided buffer path.  Oracle: the same words channel-planar."""
+    from tests.gpu_util import dev
+    rng = np.random.default_rng(cap + 17 * (direction == "gather"))
+    sizes = np.array([cap, 1, 0, cap - 3, 65, cap // 2])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    pi = np.concatenate([rng.permutation(int(s)) for s in sizes]).astype(np.int32)
+    x = rng.standard_normal(n)                                  # float64
+    got = ts.tile_permute(dev(x), dev(pi), direction, dev(off), max_tile_len=cap)
+    ts.check_device_errors()
+    words = x.view(np.uint32).reshape(n, 2).T.copy()            # [2, N] planar words
+    d = oracle.SCATTER if direction == "scatter" else oracle.GATHER
+    want = oracle.tile_permute(words, pi, d, off, nthreads=8)
+    assert np.array_equal(got.cpu().numpy().view(np.uint32).reshape(n, 2).T, want)

@@ -201,3 +201,22 @@ def test_merge_one_large_array(ts, oracle):
     payload = rng.integers(0, 2**32, size=n, dtype=np.uint32)
     off = np.array([0, n], np.int64)
     run_and_compare(ts, oracle, keys, payload, off, "merge", max_len=n)
+
+
+@pytest.mark.parametrize("schedule", ["bitonic", "split", "merge", "naive"])
+def test_64bit_payload(ts, oracle, schedule):
+    """A float64 payload (two 32-bit words per element, elem_stride 2) follows the sort."""
+    from tests.gpu_util import dev
+    rng = np.random.default_rng(77)
+    cap = 4096 if schedule == "bitonic" else 8192
+    sizes = np.array([cap, 1, 0, 3000, cap - 1, 700])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    keys = rng.integers(0, 1000, size=n, dtype=np.uint32)      # many ties
+    pay = rng.standard_normal(n)                               # float64
+    k, p, perm = ts.tile_sort(dev(keys), dev(pay), dev(off), max_tile_len=cap, schedule=schedule)
+    ts.check_device_errors()
+    wk, wp, wperm = oracle.tile_sort(keys, pay.view(np.uint32).reshape(n, 2).T.copy(), off)
+    assert np.array_equal(k.cpu().numpy().view(np.uint32), wk)
+    assert np.array_equal(perm.cpu().numpy(), wperm)
+    assert np.array_equal(p.cpu().numpy().view(np.uint32).reshape(n, 2).T, wp)
