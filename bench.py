@@ -225,7 +225,7 @@ def bench_c1(torch, ts, inputs):
     do = torch.from_numpy(off).cuda()
     ko, po, pm = torch.empty_like(dk), torch.empty_like(dp), torch.empty_like(dk)
     out = {}
-    for sched in ("bitonic", "split", "merge", "naive"):
+    for sched in ("auto", "bitonic", "split", "merge", "naive"):
         _, m, _ = timed_launches(lambda: ts.tile_sort(dk, dp, do, max_tile_len=4096, schedule=sched,
                                                       keys_out=ko, payload_out=po, perm_out=pm),
                                  200, 20, torch)

@@ -229,6 +229,8 @@ ts_status ts_lds_probe(const uint32_t* lane_words, int op, int width, int iters,
       schedule, 0: one tile per wavefront.
    "sort_plan_4096", "sort_plan_8192", "sort_plan_16384" -- the TS_SCHED_* value that
       tile_sort's AUTO uses for max_tile_len up to that length.
+   "sort_small_batch" -- AUTO sorts batches of at most this many tiles of up to 4096
+      keys with TS_SCHED_SPLIT (lower latency per tile); default 1024, 0 disables.
    Returns TS_ERR_INVALID for an unknown knob or value. */
 ts_status ts_tune(const char* knob, int value);
 

@@ -42,10 +42,15 @@ int sched_of(uint32_t flags) { return (int)((flags >> 8) & 0xFu); }
 // ts_tune("sort_plan_<len>", schedule).
 int g_sort_plan[3] = {TS_SCHED_BITONIC, TS_SCHED_MERGE, TS_SCHED_MERGE};
 
-int resolve_sort_sched(uint32_t flags, int64_t max_len) {
+// AUTO sorts a batch of at most this many tiles of up to 4096 keys with SPLIT: eight
+// waves per tile finish one tile sooner than one wave running a network, while large
+// batches are throughput-bound and take the tuned plan (tuning knob "sort_small_batch").
+int64_t g_sort_small_batch = 1024;
+
+int resolve_sort_sched(uint32_t flags, int64_t max_len, int64_t num_tiles) {
     const int s = sched_of(flags);
     if (s != TS_SCHED_AUTO) return s;
-    if (max_len <= 4096) return g_sort_plan[0];
+    if (max_len <= 4096) return num_tiles <= g_sort_small_batch ? TS_SCHED_SPLIT : g_sort_plan[0];
     if (max_len <= 8192) return g_sort_plan[1];
     if (max_len <= 16384) return g_sort_plan[2];
     return TS_SCHED_MERGE;
@@ -131,7 +136,7 @@ size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t tot
         (sched_of(flags) == TS_SCHED_THM2 || sched_of(flags) == TS_SCHED_BITONIC))
         return kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
     if (op != TS_OP_SORT || num_tiles <= 0 || total_len < 0) return kWorkspaceBytes;
-    const int sched = resolve_sort_sched(flags, max_tile_len);
+    const int sched = resolve_sort_sched(flags, max_tile_len, num_tiles);
     if (sched == TS_SCHED_MERGE) return ts::merge_layout(num_tiles, total_len, max_tile_len).total;
     // a payload without perm_out keeps the permutation in the workspace
     if (channels > 0) return kWorkspaceBytes + (size_t)total_len * 4u;
@@ -330,7 +335,7 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
         return fail(TS_ERR_INVALID, "tile_sort: keys_in and keys_out alias");
     st = check_payload(payload_in, payload_out, channels, elem_stride, chan_stride, true);
     if (st != TS_OK) return st;
-    const int sched = resolve_sort_sched(flags, max_tile_len);
+    const int sched = resolve_sort_sched(flags, max_tile_len, num_tiles);
     if (sched != TS_SCHED_SPLIT && sched != TS_SCHED_THM2 && sched != TS_SCHED_BITONIC &&
         sched != TS_SCHED_MERGE && sched != TS_SCHED_NAIVE)
         return fail(TS_ERR_UNSUPPORTED, "tile_sort: schedule %d not available", sched);
@@ -413,6 +418,11 @@ ts_status ts_tune(const char* knob, int value) {
         if (!(value == 0 || value == 1 || value == 2 || (value >= 6 && value <= 9)))
             return fail(TS_ERR_INVALID, "ts_tune: permute_variant must be one of 0, 1, 2, 6, 7, 8, 9");
         ts::set_permute_variant(value);
+        return TS_OK;
+    }
+    if (std::strcmp(knob, "sort_small_batch") == 0) {
+        if (value < 0) return fail(TS_ERR_INVALID, "ts_tune: sort_small_batch must be >= 0");
+        g_sort_small_batch = value;
         return TS_OK;
     }
     if (std::strcmp(knob, "merge_pack") == 0) {
