@@ -100,7 +100,7 @@ enum {
 };
 
 /* Operation ids for ts_workspace_bytes */
-enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2 };
+enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2, TS_OP_DEVICE_SORT = 3 };
 
 /*
  * tile_sort -- sorting (Sec. 1, "Problems of interest": sorting; Sec. 2, Lemma 1
@@ -164,6 +164,29 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels,
                        const int32_t* pi, uint32_t direction, int32_t* inv_out,
                        const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
                        uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * ts_device_sort -- stable ascending sort of one array of n uint32 keys (the whole
+ * array, not tiles), built on the conflict-free 64-way partition: an LSD radix sort
+ * whose every pass partitions each 4096-key tile on a 6-bit digit with the split
+ * schedule and stores each digit block at its place in the array (Sec. 1: the
+ * partition step of a quicksort with pivots, here with digit buckets).  Six passes.
+ *   keys_in / keys_out  : uint32 [n] (device, must not alias); with
+ *                         TS_FLAG_F32_ORDERED binary32 bit patterns, -0 < +0.
+ *   payload_in / out    : optional uint32 [n] moved with the keys (one word per key).
+ *   perm_out            : optional int32 [n]: source index of every output slot; not
+ *                         together with a payload (TS_ERR_UNSUPPORTED).
+ *   n                   : 0 <= n < 2^31.
+ *   workspace           : ts_workspace_bytes(TS_OP_DEVICE_SORT, flags, 1, n, n, c) bytes
+ *                         with c = 1 when a payload or perm_out is given, else 0; holds
+ *                         one ping-pong copy of the keys (and payload words) plus the
+ *                         tile histograms.
+ * Returns TS_ERR_INVALID for NULL or aliasing arrays, TS_ERR_WORKSPACE for a short
+ * workspace; the work is enqueued on `stream` (no host synchronisation).
+ */
+ts_status ts_device_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* payload_in,
+                         uint32_t* payload_out, int32_t* perm_out, int64_t n, uint32_t flags,
+                         void* workspace, size_t workspace_bytes, void* stream);
 
 /* Bytes of workspace a call of operation `op` (TS_OP_*) with these flags and sizes
    needs (never 0).  total_len is the number of items (tile_offsets[num_tiles]). */

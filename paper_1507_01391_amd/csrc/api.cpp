@@ -135,6 +135,8 @@ size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t tot
     if (op == TS_OP_PARTITION && num_tiles > 0 && channels > 0 &&
         (sched_of(flags) == TS_SCHED_THM2 || sched_of(flags) == TS_SCHED_BITONIC))
         return kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
+    if (op == TS_OP_DEVICE_SORT)
+        return total_len > 0 ? ts::device_sort_layout(total_len, channels > 0).total : kWorkspaceBytes;
     if (op != TS_OP_SORT || num_tiles <= 0 || total_len < 0) return kWorkspaceBytes;
     const int sched = resolve_sort_sched(flags, max_tile_len, num_tiles);
     if (sched == TS_SCHED_MERGE) return ts::merge_layout(num_tiles, total_len, max_tile_len).total;
@@ -440,6 +442,37 @@ ts_status ts_tune(const char* knob, int value) {
         return TS_OK;
     }
     return fail(TS_ERR_INVALID, "ts_tune: unknown knob '%s'", knob);
+}
+
+ts_status ts_device_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* payload_in,
+                         uint32_t* payload_out, int32_t* perm_out, int64_t n, uint32_t flags,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+    if (n < 0) return fail(TS_ERR_INVALID, "ts_device_sort: n < 0");
+    if (n > INT32_MAX) return fail(TS_ERR_UNSUPPORTED, "ts_device_sort: n >= 2^31");
+    if (workspace == nullptr) return fail(TS_ERR_WORKSPACE, "workspace is NULL");
+    if (n == 0) return TS_OK;
+    if (keys_in == nullptr || keys_out == nullptr) return fail(TS_ERR_INVALID, "ts_device_sort: keys are NULL");
+    if (keys_in == keys_out) return fail(TS_ERR_INVALID, "ts_device_sort: keys_in and keys_out alias");
+    if ((payload_in == nullptr) != (payload_out == nullptr))
+        return fail(TS_ERR_INVALID, "ts_device_sort: payload_in and payload_out must both be given");
+    if (payload_in != nullptr && payload_in == payload_out)
+        return fail(TS_ERR_INVALID, "ts_device_sort: payload_in and payload_out alias");
+    if (payload_in != nullptr && perm_out != nullptr)
+        return fail(TS_ERR_UNSUPPORTED, "ts_device_sort: a payload and perm_out together");
+    const bool carry = payload_in != nullptr || perm_out != nullptr;
+    const size_t need = ts::device_sort_layout(n, carry).total;
+    if (workspace_bytes < need)
+        return fail(TS_ERR_WORKSPACE, "ts_device_sort needs %zu workspace bytes (got %zu)", need, workspace_bytes);
+    ts::DeviceSortArgs d{};
+    d.keys_in = keys_in;
+    d.keys_out = keys_out;
+    d.pay_in = payload_in;
+    d.pay_out = payload_out;
+    d.perm_out = perm_out;
+    d.n = n;
+    d.f32 = (flags & TS_FLAG_F32_ORDERED) ? 1u : 0u;
+    d.err = (uint32_t*)workspace;
+    return hip_status(ts::launch_device_sort(d, workspace, (hipStream_t)stream), "ts_device_sort launch");
 }
 
 ts_status ts_copy(const void* src, void* dst, size_t bytes, void* stream) {

@@ -90,6 +90,17 @@ TS_DEV uint32_t row_prefix_sum(uint32_t v) {
     }
 }
 
+// Inclusive prefix sum across the 64 lanes of a wavefront.
+TS_DEV uint32_t wave_inclusive_scan_u32(uint32_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
 // Issue CPW coalesced 32-bit global loads of one tile, column j = items 64*(c0+j) + lane,
 // with no waits between them and no branches around them.  Element g of the tile is at
 // base[(o + g) * stride].  Lanes past the end (and every lane when n <= 0) read from

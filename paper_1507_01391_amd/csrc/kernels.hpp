@@ -60,6 +60,41 @@ struct SortArgs {
     uint32_t* err;
 };
 
+// One pass of the device-wide radix sort (device_sort.hip): tiles of 4096 items split
+// on the digit bits shift .. shift + nbits - 1 and stored by digit block at goff.
+struct RadixPass {
+    const uint32_t* keys_in;
+    uint32_t* keys_out;
+    const uint32_t* pay_in;     // or NULL
+    uint32_t* pay_out;          // or NULL
+    const int64_t* offsets;     // num_tiles + 1 tile boundaries
+    int64_t num_tiles;
+    int shift, nbits;
+    uint32_t f32_in, f32_out;   // map binary32 keys on load / back on store
+    const uint32_t* hist;
+    const uint32_t* goff;
+    int64_t n_total;
+    uint32_t* err;
+};
+hipError_t launch_radix_pass(const RadixPass& r, hipStream_t s);
+constexpr int RADIX_TILE = 4096;
+
+struct DeviceSortArgs {
+    const uint32_t* keys_in;
+    uint32_t* keys_out;
+    const uint32_t* pay_in;     // one payload word per key, or NULL
+    uint32_t* pay_out;
+    int32_t* perm_out;          // or NULL; not together with a payload
+    int64_t n;
+    uint32_t f32;
+    uint32_t* err;
+};
+struct DeviceSortLayout {
+    size_t offsets, hist, goff, bsum, keys, pay, total;
+};
+DeviceSortLayout device_sort_layout(int64_t n, bool with_pay);
+hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s);
+
 // Sorting tiles of uneven length by pieces and merges (merge.hip).
 constexpr int MERGE_PIECE = 4096;          // keys per wavefront work item
 constexpr int MERGE_POS_BITS = 28;         // tile positions fit in 28 bits

@@ -35,9 +35,11 @@ namespace ts {
 
 namespace {
 
-// Arguments of the split kernel, for both uses: the stable partition (MODE 0: item =
-// label + position + one payload word) and the LSD radix sort of 32-bit keys (MODE 1:
-// item = ordered key + position).
+// Arguments of the split kernel, for its three uses: the stable partition (MODE 0: item
+// = label + position + one payload word), the LSD radix sort of 32-bit keys in a tile
+// (MODE 1: item = ordered key + position) and one pass of the device-wide radix sort
+// (MODE 2: item = ordered key + payload word; the tile is split on one digit and every
+// digit block is stored at its place in the whole array).
 struct SplitArgs {
     const uint32_t* keys_in;    // labels or keys
     uint32_t* keys_out;
@@ -50,8 +52,14 @@ struct SplitArgs {
     uint32_t num_classes;       // MODE 0: labels must be below this
     int nbits;                  // bits to split on
     uint32_t validate;
-    uint32_t f32;               // MODE 1: keys are binary32 patterns
+    uint32_t f32;               // MODE 1: keys are binary32 patterns; MODE 2: map them on load
     uint32_t* err;
+    // MODE 2 only
+    int shift;                  // the digit is bits shift .. shift + nbits - 1 of the key
+    uint32_t f32_out;           // map ordered keys back to binary32 on store
+    const uint32_t* hist;       // [64][num_tiles] digit counts of every tile (digit-major)
+    const uint32_t* goff;       // [64][num_tiles] exclusive prefix of hist in that order
+    int64_t n_total;            // length of the whole array (destinations are below it)
 };
 
 template <int CPW>
@@ -138,8 +146,10 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
                 } else if (a.f32) {
                     lab = f32_to_ordered(lab);
                 }
+                if (MODE == 2) pay = has_pay ? L.pay[j] : (uint32_t)(o + i);  // no payload: the index
             }
-            e[j] = (MODE == 0) ? pack(((uint32_t)i << 16) | lab, pay) : pack(lab, (uint32_t)i);
+            e[j] = (MODE == 0) ? pack(((uint32_t)i << 16) | lab, pay)
+                               : pack(lab, MODE == 2 ? pay : (uint32_t)i);
         }
         if (a.validate) flag_error(a.err, bad, ERR_BAD_LABEL);
 
@@ -152,6 +162,7 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
         const uint32_t lane8 = (uint32_t)lane * 8u;
         const uint32_t neg_lane8 = 0u - lane8;
         const uint32_t fwd_base = lane8 + (uint32_t)(w * CPW * 512);  // column j at + 512 j
+        const int bit0 = (MODE == 2) ? a.shift : 0;
         for (int b = 0; b < a.nbits; ++b) {
             // Zero masks of this wave's columns; zeros before this wave's first column (zb)
             // and in the whole tile (zt).
@@ -162,7 +173,7 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
                 int zc = 0;
 #pragma unroll
                 for (int j = 0; j < CPW; ++j) {
-                    zm[j] = ballot(((hi32(e[j]) >> b) & 1u) == 0u);
+                    zm[j] = ballot(((hi32(e[j]) >> (b + bit0)) & 1u) == 0u);
                     zc += popc64(zm[j]);
                 }
                 if (lane == 0) wz[w] = zc;
@@ -183,7 +194,7 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
                 const int k = w * CPW + j;
-                const uint64_t zj = KEEP ? zm[KEEP ? j : 0] : ballot(((hi32(e[j]) >> b) & 1u) == 0u);
+                const uint64_t zj = KEEP ? zm[KEEP ? j : 0] : ballot(((hi32(e[j]) >> (b + bit0)) & 1u) == 0u);
                 const uint32_t one_off = zero_if_mask(zj, (uint32_t)(N - 1 - 64 * k) - (uint32_t)lane);
                 const uint32_t pos = count_below_plus(zj, one_off) + (uint32_t)z;
                 lds_store(A, pos * 8u, e[j]);
@@ -213,6 +224,30 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
             }
         }
 
+        if constexpr (MODE == 2) {
+            // ---- digit d's block of this tile goes to goff[d][t] + (rank inside the
+            //      block): lane d holds goff[d][t] minus the block's first slot in the
+            //      tile, and every item fetches its digit's value with ds_bpermute
+            const int ls = (int)opaque((uint32_t)lane);
+            const int64_t T = a.num_tiles;
+            const uint32_t cnt = a.hist[(int64_t)ls * T + t];
+            const uint32_t delta = a.goff[(int64_t)ls * T + t] - (wave_inclusive_scan_u32(cnt) - cnt);
+            const uint32_t dmask = (1u << a.nbits) - 1u;
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int v = 64 * (w * CPW + j) + ls;
+                const uint32_t h = hi32(e[j]);
+                const uint32_t d = (h >> a.shift) & dmask;
+                const int64_t dst = (int64_t)(uint32_t)__builtin_amdgcn_ds_bpermute((int)(d * 4u), (int)delta) + v;
+                if (v < n && dst < a.n_total) {
+                    a.keys_out[dst] = a.f32_out ? ordered_to_f32(h) : h;
+                    if (a.pay_out) a.pay_out[dst] = lo32(e[j]);
+                }
+                // counts that disagree with the tile would send a key past the end: not
+                // stored, recorded instead
+                if (a.validate) flag_error(a.err, v < n && dst >= a.n_total, ERR_BAD_OFFSETS);
+            }
+        } else
         // ---- store in order (coalesced: column k covers items 64k .. 64k+63), one
         //      uniform branch per output; stores past the end of the tile are dropped by
         //      the buffer range check
@@ -326,6 +361,29 @@ hipError_t launch_partition_split(const PartitionArgs& p, int64_t max_len, hipSt
     }
     if (max_len <= 8192) return launch_split_shaped<8, 8192>(a, o, s);
     return launch_split_shaped<16, 16384>(a, o, s);
+}
+
+hipError_t launch_radix_pass(const RadixPass& r, hipStream_t s) {
+    if (r.num_tiles == 0) return hipSuccess;
+    SplitArgs a{};
+    a.keys_in = r.keys_in;
+    a.keys_out = r.keys_out;
+    a.pay_in = r.pay_in;
+    a.pay_out = r.pay_out;
+    a.pay_es = 1;
+    a.has_pay = r.pay_in != nullptr;
+    a.num_tiles = r.num_tiles;
+    a.nbits = r.nbits;
+    a.f32 = r.f32_in;
+    a.err = r.err;
+    a.shift = r.shift;
+    a.f32_out = r.f32_out;
+    a.hist = r.hist;
+    a.goff = r.goff;
+    a.n_total = r.n_total;
+    a.validate = 1;
+    static_assert(RADIX_TILE == 4096, "the pass kernel holds 4096-item tiles");
+    return launch_split<8, 4096, 8, 2, 0, 0, true>(a, r.offsets, s);
 }
 
 hipError_t launch_sort_split(const SortArgs& q, int64_t max_len, hipStream_t s) {

@@ -194,6 +194,36 @@ def tile_sort(keys: torch.Tensor, payload: Optional[torch.Tensor] = None, offset
     return keys_out, payload_out, perm_out
 
 
+def device_sort(keys: torch.Tensor, payload: Optional[torch.Tensor] = None, want_perm: bool = False,
+                f32_ordered: bool = False, keys_out: Optional[torch.Tensor] = None,
+                payload_out: Optional[torch.Tensor] = None, perm_out: Optional[torch.Tensor] = None):
+    """Stable ascending sort of one whole array of 32-bit keys (ts_device_sort): an LSD
+    radix sort whose passes are conflict-free 64-way tile partitions.  ``payload`` is an
+    optional [N] 32-bit tensor moved with the keys; ``want_perm`` returns the source index
+    of every output slot (not together with a payload).  Returns (keys_out, payload_out
+    or None, perm or None)."""
+    keys = _as_words(keys, "keys")
+    assert keys.dim() == 1
+    n = keys.shape[0]
+    dev = keys.device
+    if payload is not None:
+        payload = _as_words(payload, "payload")
+        assert payload.shape == keys.shape, "one payload word per key"
+        if payload_out is None:
+            payload_out = torch.empty_like(payload)
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if want_perm and perm_out is None:
+        perm_out = torch.empty(n, dtype=torch.int32, device=dev)
+    flags = _lib.TS_FLAG_F32_ORDERED if f32_ordered else 0
+    lib = _lib.load()
+    carry = 1 if (payload is not None or perm_out is not None) else 0
+    ws = workspace(dev, lib.ts_workspace_bytes(_lib.TS_OP_DEVICE_SORT, flags, 1, n, n, carry))
+    _lib.check(lib.ts_device_sort(_ptr(keys), _ptr(keys_out), _ptr(payload), _ptr(payload_out),
+                                  _ptr(perm_out), n, flags, _ptr(ws), ws.numel() * 4, _stream(dev)))
+    return keys_out, payload_out, perm_out
+
+
 def copy(src: torch.Tensor, dst: torch.Tensor) -> None:
     """HBM reference copy (16-byte vector loads and stores)."""
     assert src.is_cuda and dst.is_cuda and src.numel() * src.element_size() <= dst.numel() * dst.element_size()

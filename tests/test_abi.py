@@ -128,3 +128,21 @@ def test_permute_argument_validation(lib):
     # tiles longer than the routing capacity
     rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, pi, 0, None, fake, 1, 32768, 0, ws, 256, None)
     assert rc == 2
+
+
+def test_device_sort_argument_validation(lib):
+    P = ctypes.c_void_p
+    keys, out, pay, pout, perm, ws = P(0x1000), P(0x2000), P(0x3000), P(0x4000), P(0x5000), P(0x8000)
+    big = 1 << 40
+    assert lib.ts_device_sort(keys, out, None, None, None, -1, 0, ws, big, None) == 1
+    assert lib.ts_device_sort(keys, out, None, None, None, 1 << 31, 0, ws, big, None) == 2
+    assert lib.ts_device_sort(keys, keys, None, None, None, 100, 0, ws, big, None) == 1      # alias
+    assert lib.ts_device_sort(None, out, None, None, None, 100, 0, ws, big, None) == 1
+    assert lib.ts_device_sort(keys, out, pay, None, None, 100, 0, ws, big, None) == 1        # half a payload
+    assert lib.ts_device_sort(keys, out, pay, pay, None, 100, 0, ws, big, None) == 1         # payload alias
+    assert lib.ts_device_sort(keys, out, pay, pout, perm, 100, 0, ws, big, None) == 2        # payload + perm
+    need = lib.ts_workspace_bytes(3, 0, 1, 100, 100, 1)
+    assert need >= 256 + 100 * 8
+    assert lib.ts_device_sort(keys, out, None, None, perm, 100, 0, ws, need - 1, None) == 4  # workspace
+    assert lib.ts_device_sort(keys, out, None, None, None, 0, 0, ws, 0, None) == 0           # empty: nothing to do
+    assert lib.ts_device_sort(keys, out, None, None, None, 100, 0, None, big, None) == 4

@@ -1,0 +1,72 @@
+"""GPU parity of ts_device_sort (one whole array, LSD passes of conflict-free tile
+partitions) against the CPU oracle's stable sort, bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ts():
+    import paper_1507_01391_amd as ts
+    return ts
+
+
+def dev(a):
+    from tests.gpu_util import dev as d
+    return d(a)
+
+
+@pytest.mark.parametrize("n", [1, 63, 4095, 4096, 4097, 12289, 100003, (1 << 20) + 123])
+def test_keys_and_payload(ts, oracle, n):
+    rng = np.random.default_rng(n)
+    keys = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    pay = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    k, p, _ = ts.device_sort(dev(keys), dev(pay))
+    ts.check_device_errors()
+    wk, wp, _ = oracle.tile_sort(keys, pay, nthreads=8)
+    assert np.array_equal(k.cpu().numpy().view(np.uint32), wk)
+    assert np.array_equal(p.cpu().numpy().view(np.uint32), wp)
+
+
+@pytest.mark.parametrize("distinct", [1, 3, 64, 1000])
+def test_permutation_with_ties(ts, oracle, distinct):
+    """Heavy ties: the permutation pins stability (equal keys keep input order)."""
+    n = 50000
+    rng = np.random.default_rng(distinct)
+    keys = (rng.integers(0, distinct, size=n, dtype=np.uint32) * np.uint32(2654435761)).astype(np.uint32)
+    k, _, perm = ts.device_sort(dev(keys), want_perm=True)
+    ts.check_device_errors()
+    wk, _, wperm = oracle.tile_sort(keys, nthreads=8)
+    assert np.array_equal(k.cpu().numpy().view(np.uint32), wk)
+    assert np.array_equal(perm.cpu().numpy(), wperm)
+
+
+def test_keys_only_and_f32(ts, oracle):
+    rng = np.random.default_rng(5)
+    n = 70000
+    keys = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    k, p, perm = ts.device_sort(dev(keys))
+    ts.check_device_errors()
+    assert p is None and perm is None
+    assert np.array_equal(k.cpu().numpy().view(np.uint32), np.sort(keys, kind="stable"))
+    f = rng.standard_normal(n).astype(np.float32)
+    f[:6] = [0.0, -0.0, np.inf, -np.inf, np.nan, -np.nan]
+    kf, _, pf = ts.device_sort(torch.from_numpy(f).cuda(), want_perm=True, f32_ordered=True)
+    ts.check_device_errors()
+    wk, _, wperm = oracle.tile_sort(f, f32_ordered=True, nthreads=8)
+    assert np.array_equal(kf.cpu().numpy().view(np.uint32), wk.view(np.uint32))
+    assert np.array_equal(pf.cpu().numpy(), wperm)
+
+
+def test_large_against_numpy(ts):
+    """2^24 keys with the permutation against numpy's stable argsort."""
+    n = 1 << 24
+    rng = np.random.default_rng(24)
+    keys = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    k, _, perm = ts.device_sort(dev(keys), want_perm=True)
+    ts.check_device_errors()
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(perm.cpu().numpy(), order.astype(np.int32))
+    assert np.array_equal(k.cpu().numpy().view(np.uint32), keys[order])
