@@ -182,6 +182,7 @@ def bench_c2(args, torch, ts, inputs):
         extra.update(bench_c3(args, torch, ts, inputs))
         extra.update(bench_c4(args, torch, ts, inputs, orc))
         extra.update(bench_c5(args, torch, ts, inputs))
+        extra.update(bench_device_sort(torch, ts))
 
     cpu = None
     if not args.no_cpu:
@@ -328,6 +329,31 @@ def bench_c4(args, torch, ts, inputs, orc):
            "c4_ms_per_replay": m, "c4_keys": n, "c4_segments": S,
            "c4_parity_sampled_segments": "16 segments bit-exact" if ok else "MISMATCH"}
     del g, dk, dp, do, ko, po, pm
+    return out
+
+
+def bench_device_sort(torch, ts, n=1 << 28):
+    """One array of 2^28 uint32 keys with a 32-bit payload sorted as a whole
+    (ts_device_sort: LSD passes of conflict-free tile partitions); torch.sort(stable) on
+    the same keys (values + int64 indices) is timed beside it as a library reference."""
+    rng = np.random.default_rng(1507 + 6)
+    keys = torch.from_numpy(rng.integers(0, 2**32, size=n, dtype=np.uint32).view(np.int32)).cuda()
+    pay = torch.arange(n, dtype=torch.int32, device="cuda")
+    ko, po = torch.empty_like(keys), torch.empty_like(pay)
+    log(f"[bench] device-wide sort of 2^{n.bit_length() - 1} keys ...")
+    _, m, _ = timed_launches(lambda: ts.device_sort(keys, pay, keys_out=ko, payload_out=po), 5, 2, torch)
+    # sampled parity: the output is sorted and each payload word points at its key
+    ts.check_device_errors()
+    idx = torch.from_numpy(np.sort(rng.choice(n - 1, size=4096, replace=False))).cuda()
+    kk = ko.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    ok = bool((kk[idx] <= kk[idx + 1]).all().item()) and \
+        bool(((keys.to(torch.int64) & 0xFFFFFFFF)[po[idx].to(torch.int64)] == kk[idx]).all().item())
+    _, m2, _ = timed_launches(lambda: torch.sort(keys, stable=True), 5, 2, torch)
+    out = {"device_sort_keys": n, "device_sort_keys_payload_per_s": n / (m / 1e3),
+           "device_sort_ms": m, "device_sort_sampled_check": "ok" if ok else "MISMATCH",
+           "torch_sort_stable_int32_per_s": n / (m2 / 1e3)}
+    del keys, pay, ko, po
+    torch.cuda.empty_cache()
     return out
 
 
