@@ -51,6 +51,17 @@ TS_DEV int64_t opaque_s64(int64_t v) {
     return v;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b % 8),
+// each with its own L2.  For a grid of g workgroups with one tile each, this gives XCD
+// x one contiguous range of tiles, taken in order: tiles that write neighbouring parts
+// of one cache line then run on the same XCD at about the same time.  A bijection of
+// [0, g): XCD x holds g/8 (+1 if x < g%8) workgroups and its range starts at
+// x*(g/8) + min(x, g%8).
+TS_DEV int64_t xcd_contiguous(int64_t b, int64_t g) {
+    const int64_t x = b & 7, i = b >> 3, q = g >> 3, r = g & 7;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // Cross-lane exchange through LDS inside one wavefront.  The LDS executes a
 // wavefront's instructions in order, so no hardware wait is needed; what must be
 // stopped is the compiler moving loads and stores across this point: it reasons per

@@ -1,14 +1,14 @@
 // Device-wide stable sort of one array of 32-bit keys (with an optional payload word
-// or the permutation), built on the conflict-free 64-way partition of tiles.
+// or the permutation), built on the conflict-free partition of tiles.
 //
 // Afshani & Sitchinava (Sec. 1) note that partitioning is the step of a quicksort with
 // pivots: every row sends its items to the bucket of their range.  Here the buckets are
-// the values of a 6-bit digit of the key and the sort is LSD: six passes (digits of
-// 6, 6, 6, 6, 6 and 2 bits).  A pass
+// the values of a 6-bit digit of the key and the sort is LSD: six passes (digits of 6,
+// 6, 6, 6, 6 and 2 bits).  A pass
 //   1. counts every tile's digits (tile t, digit d -> hist[d][t]),
 //   2. takes the exclusive prefix of hist in digit-major order (goff[d][t]: where tile
 //      t's block of digit d starts in the output array),
-//   3. partitions every 4096-item tile on the digit with the conflict-free binary
+//   3. partitions every 4096-item tile on the digit with its conflict-free binary
 //      splits (partition.hip, MODE 2) and stores each digit block at goff.
 // Each tile partition is stable and the blocks of one digit are laid out in tile order,
 // so every pass is a stable partition of the whole array and six passes sort it.
@@ -31,21 +31,23 @@ __global__ void radix_offsets_kernel(int64_t* offs, int64_t T, int64_t n) {
     if (t <= T) offs[t] = std::min<int64_t>(t * RADIX_TILE, n);
 }
 
-// hist[d][t] = number of keys of tile t whose digit is d (digits >= 2^nbits: 0).
+// hist[d][t] = number of keys of tile t whose digit is d (digits >= 2^nbits: 0).  Each
+// wave counts into a table of its own with LDS atomics; the tables are then summed.
 __global__ __launch_bounds__(HIST_NW * 64) void radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                                    int64_t n, int64_t T, int shift,
                                                                    int nbits, uint32_t f32,
                                                                    uint32_t* __restrict__ hist) {
-    __shared__ uint32_t cnt[HIST_NW][64];
+    __shared__ uint32_t cnt[HIST_NW][RADIX_DIGITS];
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t t = blockIdx.x;
-    cnt[w][lane] = 0;
-    __syncthreads();
+    const int64_t t = xcd_contiguous(blockIdx.x, gridDim.x);  // grid = T, one tile each
     const int64_t o = t * RADIX_TILE;
     const uint32_t len = (uint32_t)std::min<int64_t>(RADIX_TILE, n - o);
     uint32_t k[HIST_CPW];
-    buffer_load_columns<HIST_CPW>(buffer_rsrc(keys + o, len * 4u), ((uint32_t)(64 * w * HIST_CPW) + (uint32_t)lane) * 4u, k);
+    buffer_load_columns<HIST_CPW, true>(buffer_rsrc(keys + o, len * 4u), ((uint32_t)(64 * w * HIST_CPW) + (uint32_t)lane) * 4u, k);
+#pragma unroll
+    for (int q = 0; q < RADIX_DIGITS / 64; ++q) cnt[w][64 * q + lane] = 0;
+    __syncthreads();
     const uint32_t dmask = (1u << nbits) - 1u;
 #pragma unroll
     for (int j = 0; j < HIST_CPW; ++j) {
@@ -54,11 +56,11 @@ __global__ __launch_bounds__(HIST_NW * 64) void radix_hist_kernel(const uint32_t
         if (i < len) atomicAdd(&cnt[w][(key >> shift) & dmask], 1u);
     }
     __syncthreads();
-    if (w == 0) {
+    for (int d = (int)threadIdx.x; d < RADIX_DIGITS; d += HIST_NW * 64) {
         uint32_t sum = 0;
 #pragma unroll
-        for (int q = 0; q < HIST_NW; ++q) sum += cnt[q][lane];
-        hist[(int64_t)lane * T + t] = sum;
+        for (int q = 0; q < HIST_NW; ++q) sum += cnt[q][d];
+        hist[(int64_t)d * T + t] = sum;
     }
 }
 
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_apply_kernel(const uint32_t
 DeviceSortLayout device_sort_layout(int64_t n, bool with_pay) {
     DeviceSortLayout L{};
     const int64_t T = (n + RADIX_TILE - 1) / RADIX_TILE;
-    const int64_t m = 64 * T;
+    const int64_t m = (int64_t)RADIX_DIGITS * T;
     const int64_t nb = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     size_t off = 256;  // header: error word
@@ -171,24 +173,24 @@ hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s) 
     uint32_t* tk = (uint32_t*)(w + L.keys);
     uint32_t* tp = carry ? (uint32_t*)(w + L.pay) : nullptr;
     const int64_t T = (n + RADIX_TILE - 1) / RADIX_TILE;
-    const int64_t m = 64 * T;
+    const int64_t m = (int64_t)RADIX_DIGITS * T;
     const int64_t nb = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
     uint32_t* out_pay = d.pay_out ? d.pay_out : (uint32_t*)d.perm_out;  // final payload words
 
     hipLaunchKernelGGL(radix_offsets_kernel, dim3((unsigned)((T + 1 + 255) / 256)), dim3(256), 0, s, offs, T, n);
     hipError_t e = hipGetLastError();
-    // digits: 6, 6, 6, 6, 6, 2 bits; buffers: in -> ws, ws -> out, out -> ws, ..., ws -> out
-    static const int kShift[6] = {0, 6, 12, 18, 24, 30};
-    static const int kBits[6] = {6, 6, 6, 6, 6, 2};
-    for (int p = 0; p < 6 && e == hipSuccess; ++p) {
+    // buffers: in -> ws, ws -> out, out -> ws, ..., ws -> out
+    constexpr int kPasses = RADIX_PASSES;
+    static_assert(kPasses % 2 == 0, "an even number of passes ends in the output");
+    for (int p = 0; p < kPasses && e == hipSuccess; ++p) {
         const bool to_ws = (p % 2) == 0;
         const uint32_t* kin = p == 0 ? d.keys_in : (to_ws ? d.keys_out : tk);
         const uint32_t* pin = p == 0 ? d.pay_in : (to_ws ? out_pay : tp);
         uint32_t* kout = to_ws ? tk : d.keys_out;
         uint32_t* pout = carry ? (to_ws ? tp : out_pay) : nullptr;
         const uint32_t f32_in = (p == 0) ? d.f32 : 0u;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)T), dim3(HIST_NW * 64), 0, s, kin, n, T, kShift[p],
-                           kBits[p], f32_in, hist);
+        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)T), dim3(HIST_NW * 64), 0, s, kin, n, T,
+                           RADIX_BITS * p, std::min(RADIX_BITS, 32 - RADIX_BITS * p), f32_in, hist);
         hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum);
         hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
         hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum, goff);
@@ -201,10 +203,10 @@ hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s) 
         r.pay_out = pout;
         r.offsets = offs;
         r.num_tiles = T;
-        r.shift = kShift[p];
-        r.nbits = kBits[p];
+        r.shift = RADIX_BITS * p;
+        r.nbits = std::min(RADIX_BITS, 32 - RADIX_BITS * p);
         r.f32_in = f32_in;
-        r.f32_out = (p == 5) ? d.f32 : 0u;
+        r.f32_out = (p == kPasses - 1) ? d.f32 : 0u;
         r.hist = hist;
         r.goff = goff;
         r.n_total = n;

@@ -57,8 +57,8 @@ struct SplitArgs {
     // MODE 2 only
     int shift;                  // the digit is bits shift .. shift + nbits - 1 of the key
     uint32_t f32_out;           // map ordered keys back to binary32 on store
-    const uint32_t* hist;       // [64][num_tiles] digit counts of every tile (digit-major)
-    const uint32_t* goff;       // [64][num_tiles] exclusive prefix of hist in that order
+    const uint32_t* hist;       // [RADIX_DIGITS][num_tiles] digit counts of every tile
+    const uint32_t* goff;       // [RADIX_DIGITS][num_tiles] exclusive prefix of hist in that order
     int64_t n_total;            // length of the whole array (destinations are below it)
 };
 
@@ -110,7 +110,10 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
     const bool has_pay = a.has_pay != 0;
 
     TileLoad<CPW> L;
-    int64_t t = blockIdx.x;
+    // A radix pass runs one workgroup per tile (grid = num_tiles), XCD-contiguous: the
+    // digit blocks of neighbouring tiles share cache lines of the output and of the
+    // count tables.
+    int64_t t = (MODE == 2) ? xcd_contiguous(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     issue_tile_load<CPW, CAP, NTL>(a, offs, t, w0, lane0, L);
 
     for (; t < a.num_tiles; t += gridDim.x) {
@@ -152,6 +155,20 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
                                : pack(lab, MODE == 2 ? pay : (uint32_t)i);
         }
         if (a.validate) flag_error(a.err, bad, ERR_BAD_LABEL);
+
+        // ---- radix pass: lane l, quarter q stands for digit d = 64q + l; its count and
+        //      output offset in this tile are loaded now, so that they arrive while the
+        //      tile is split
+        constexpr int RQ = (MODE == 2) ? RADIX_DIGITS / 64 : 1;
+        uint32_t rcnt[RQ], rgoff[RQ];
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) {
+                const int64_t idx = (int64_t)(64 * q + lane) * a.num_tiles + t;
+                rcnt[q] = a.hist[idx];
+                rgoff[q] = a.goff[idx];
+            }
+        }
 
         // ---- prefetch the next tile while this one is split in LDS
         if (PREFETCH) issue_tile_load<CPW, CAP, NTL>(a, offs, t + gridDim.x, w, lane, L);
@@ -225,20 +242,34 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
         }
 
         if constexpr (MODE == 2) {
-            // ---- digit d's block of this tile goes to goff[d][t] + (rank inside the
-            //      block): lane d holds goff[d][t] minus the block's first slot in the
-            //      tile, and every item fetches its digit's value with ds_bpermute
+            // ---- digit d's block of this tile goes to goff[d][t] onward; in the split
+            //      tile it starts after the blocks of the smaller digits, so the item of
+            //      digit d at tile rank v goes to v + delta[d], delta[d] = goff[d][t] -
+            //      (counts of the digits below d).  Every item fetches delta of its digit
+            //      from lane d mod 64 of quarter d / 64 with ds_bpermute (no bank conflicts).
+            uint32_t delta[RQ];
+            uint32_t below = 0;  // counts of the digits of the previous quarters
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) {
+                const uint32_t inc = wave_inclusive_scan_u32(rcnt[q]);
+                delta[q] = rgoff[q] - (below + inc - rcnt[q]);
+                below += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+            }
             const int ls = (int)opaque((uint32_t)lane);
-            const int64_t T = a.num_tiles;
-            const uint32_t cnt = a.hist[(int64_t)ls * T + t];
-            const uint32_t delta = a.goff[(int64_t)ls * T + t] - (wave_inclusive_scan_u32(cnt) - cnt);
             const uint32_t dmask = (1u << a.nbits) - 1u;
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
                 const int v = 64 * (w * CPW + j) + ls;
                 const uint32_t h = hi32(e[j]);
                 const uint32_t d = (h >> a.shift) & dmask;
-                const int64_t dst = (int64_t)(uint32_t)__builtin_amdgcn_ds_bpermute((int)(d * 4u), (int)delta) + v;
+                const int src = (int)((d & 63u) * 4u);
+                uint32_t dl = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)delta[0]);
+#pragma unroll
+                for (int q = 1; q < RQ; ++q) {
+                    const uint32_t x = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)delta[q]);
+                    dl = ((d >> 6) == (uint32_t)q) ? x : dl;
+                }
+                const int64_t dst = (int64_t)(dl + (uint32_t)v);
                 if (v < n && dst < a.n_total) {
                     a.keys_out[dst] = a.f32_out ? ordered_to_f32(h) : h;
                     if (a.pay_out) a.pay_out[dst] = lo32(e[j]);
@@ -383,7 +414,7 @@ hipError_t launch_radix_pass(const RadixPass& r, hipStream_t s) {
     a.n_total = r.n_total;
     a.validate = 1;
     static_assert(RADIX_TILE == 4096, "the pass kernel holds 4096-item tiles");
-    return launch_split<8, 4096, 8, 2, 0, 0, true>(a, r.offsets, s);
+    return launch_split<8, 4096, 8, 2, 0, 1, true>(a, r.offsets, s);
 }
 
 hipError_t launch_sort_split(const SortArgs& q, int64_t max_len, hipStream_t s) {

@@ -10,6 +10,7 @@ in a fixed order, so counter rows map to patterns by dispatch order (PROBE_PATTE
     python -m paper_1507_01391_amd.profile_run permute --n 16384 --tiles 1024 --channels 8
     python -m paper_1507_01391_amd.profile_run sort --schedule bitonic --tiles 16384
     python -m paper_1507_01391_amd.profile_run segments --segments 20000
+    python -m paper_1507_01391_amd.profile_run device_sort --n 268435456 --payload
     python -m paper_1507_01391_amd.profile_run copy --bytes 1073741824
     python -m paper_1507_01391_amd.profile_run probe
 """
@@ -115,6 +116,15 @@ def run_segments(a):
                                   keys_out=ko, payload_out=po, perm_out=pm), a.reps)
 
 
+def run_device_sort(a):
+    rng = np.random.default_rng(inputs.SEED_BASE + 6)
+    keys = _dev(rng.integers(0, 2**32, size=a.n, dtype=np.uint32))
+    pay = torch.arange(a.n, dtype=torch.int32, device="cuda") if a.payload else None
+    ko = torch.empty_like(keys)
+    po = torch.empty_like(keys) if a.payload else None
+    _repeat(lambda: ops.device_sort(keys, pay, keys_out=ko, payload_out=po), a.reps)
+
+
 def run_copy(a):
     src = torch.empty(a.bytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -149,6 +159,9 @@ def main(argv=None):
     p = sub.add_parser("segments")
     p.add_argument("--schedule", default="merge")
     p.add_argument("--segments", type=int, default=20000)
+    p = sub.add_parser("device_sort")
+    p.add_argument("--n", type=int, default=1 << 28)
+    p.add_argument("--payload", action="store_true")
     p = sub.add_parser("copy")
     p.add_argument("--bytes", type=int, default=1 << 30)
     sub.add_parser("probe")
@@ -156,7 +169,7 @@ def main(argv=None):
         sp.add_argument("--reps", type=int, default=2)
     a = ap.parse_args(argv)
     {"partition": run_partition, "permute": run_permute, "sort": run_sort,
-     "segments": run_segments, "copy": run_copy, "probe": run_probe}[a.cmd](a)
+     "segments": run_segments, "device_sort": run_device_sort, "copy": run_copy, "probe": run_probe}[a.cmd](a)
     print(f"done {a.cmd}", file=sys.stderr, flush=True)
 
 
