@@ -22,8 +22,8 @@ namespace ts {
 
 namespace {
 
-constexpr int HIST_NW = 8;
-constexpr int HIST_CPW = RADIX_TILE / 64 / HIST_NW;
+constexpr int HIST_CPL = RADIX_TILE / 64;  // keys per lane: one wavefront per tile
+static_assert(RADIX_DIGITS == 64, "lane d sums the counts of digit d");
 
 // offs[t] = min(t * 4096, n) for t = 0 .. T.
 __global__ void radix_offsets_kernel(int64_t* offs, int64_t T, int64_t n) {
@@ -31,37 +31,43 @@ __global__ void radix_offsets_kernel(int64_t* offs, int64_t T, int64_t n) {
     if (t <= T) offs[t] = std::min<int64_t>(t * RADIX_TILE, n);
 }
 
-// hist[d][t] = number of keys of tile t whose digit is d (digits >= 2^nbits: 0).  Each
-// wave counts into a table of its own with LDS atomics; the tables are then summed.
-__global__ __launch_bounds__(HIST_NW * 64) void radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                                   int64_t n, int64_t T, int shift,
-                                                                   int nbits, uint32_t f32,
-                                                                   uint32_t* __restrict__ hist) {
-    __shared__ uint32_t cnt[HIST_NW][RADIX_DIGITS];
+// hist[d][t] = number of keys of tile t whose digit is d (digits >= 2^nbits: 0).  One
+// wavefront per tile.  Lane l counts its 64 keys into a column of its own of an LDS
+// table (word 64 d + l): the 64 adds of one instruction hit 64 distinct words whose
+// banks (word mod 32) differ inside each 32-lane half, so there are no bank conflicts.
+// Lane d then sums row d with 64-bit reads in the order skewed by d, so that the 32
+// lanes of a phase read 8-byte slots 32 d + ((k + d) mod 32): distinct modulo 32.
+__global__ __launch_bounds__(64) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
+                                                        int64_t T, int shift, int nbits, uint32_t f32,
+                                                        uint32_t* __restrict__ hist) {
+    __shared__ uint64_t cnt[RADIX_DIGITS * 64 / 2];
     const int lane = lane_id();
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t t = xcd_contiguous(blockIdx.x, gridDim.x);  // grid = T, one tile each
     const int64_t o = t * RADIX_TILE;
     const uint32_t len = (uint32_t)std::min<int64_t>(RADIX_TILE, n - o);
-    uint32_t k[HIST_CPW];
-    buffer_load_columns<HIST_CPW, true>(buffer_rsrc(keys + o, len * 4u), ((uint32_t)(64 * w * HIST_CPW) + (uint32_t)lane) * 4u, k);
+    uint32_t k[HIST_CPL];
+    buffer_load_columns<HIST_CPL, true>(buffer_rsrc(keys + o, len * 4u), (uint32_t)lane * 4u, k);
+    // clear: lane l writes slot 64 r + l (words 128 r + 2l, +1): 16 lanes of a 64-bit
+    // write phase cover 16 consecutive slots
 #pragma unroll
-    for (int q = 0; q < RADIX_DIGITS / 64; ++q) cnt[w][64 * q + lane] = 0;
-    __syncthreads();
+    for (int r = 0; r < RADIX_DIGITS / 2; ++r) lds_store(cnt, (uint32_t)(64 * r + lane) * 8u, uint64_t(0));
+    wave_lds_fence();
     const uint32_t dmask = (1u << nbits) - 1u;
+    uint32_t* words = (uint32_t*)cnt;
 #pragma unroll
-    for (int j = 0; j < HIST_CPW; ++j) {
-        const uint32_t i = (uint32_t)(64 * (w * HIST_CPW + j) + lane);
+    for (int j = 0; j < HIST_CPL; ++j) {
+        const uint32_t i = (uint32_t)(64 * j + lane);
         const uint32_t key = f32 ? f32_to_ordered(k[j]) : k[j];
-        if (i < len) atomicAdd(&cnt[w][(key >> shift) & dmask], 1u);
+        if (i < len) atomicAdd(&words[((key >> shift) & dmask) * 64u + (uint32_t)lane], 1u);
     }
-    __syncthreads();
-    for (int d = (int)threadIdx.x; d < RADIX_DIGITS; d += HIST_NW * 64) {
-        uint32_t sum = 0;
+    wave_lds_fence();
+    uint32_t sum = 0;
 #pragma unroll
-        for (int q = 0; q < HIST_NW; ++q) sum += cnt[q][d];
-        hist[(int64_t)d * T + t] = sum;
+    for (int q = 0; q < 32; ++q) {
+        const uint64_t v = lds_load_u64_whole(cnt, (uint32_t)(32 * lane + ((q + lane) & 31)) * 8u);
+        sum += lo32(v) + hi32(v);
     }
+    hist[(int64_t)lane * T + t] = sum;
 }
 
 // Exclusive prefix sum of m words in three launches: per-block sums, a scan of the block
@@ -189,7 +195,7 @@ hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s) 
         uint32_t* kout = to_ws ? tk : d.keys_out;
         uint32_t* pout = carry ? (to_ws ? tp : out_pay) : nullptr;
         const uint32_t f32_in = (p == 0) ? d.f32 : 0u;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)T), dim3(HIST_NW * 64), 0, s, kin, n, T,
+        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)T), dim3(64), 0, s, kin, n, T,
                            RADIX_BITS * p, std::min(RADIX_BITS, 32 - RADIX_BITS * p), f32_in, hist);
         hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum);
         hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
