@@ -335,7 +335,9 @@ def bench_c4(args, torch, ts, inputs, orc):
 def bench_device_sort(torch, ts, n=1 << 28):
     """One array of 2^28 uint32 keys with a 32-bit payload sorted as a whole
     (ts_device_sort: LSD passes of conflict-free tile partitions); torch.sort(stable) on
-    the same keys (values + int64 indices) is timed beside it as a library reference."""
+    the same keys (values + int64 indices) is timed beside it as a library reference.
+    Then one pass alone: the low 6 bits of the keys as labels, partitioned 64 ways over
+    the whole array with the payload (ts_device_partition)."""
     rng = np.random.default_rng(1507 + 6)
     keys = torch.from_numpy(rng.integers(0, 2**32, size=n, dtype=np.uint32).view(np.int32)).cuda()
     pay = torch.arange(n, dtype=torch.int32, device="cuda")
@@ -349,10 +351,22 @@ def bench_device_sort(torch, ts, n=1 << 28):
     ok = bool((kk[idx] <= kk[idx + 1]).all().item()) and \
         bool(((keys.to(torch.int64) & 0xFFFFFFFF)[po[idx].to(torch.int64)] == kk[idx]).all().item())
     _, m2, _ = timed_launches(lambda: torch.sort(keys, stable=True), 5, 2, torch)
+    # one pass alone: the whole array partitioned on a 6-bit label (ts_device_partition)
+    labels = (keys & 63).contiguous()
+    lo = torch.empty_like(labels)
+    log(f"[bench] device-wide 64-way partition of 2^{n.bit_length() - 1} labels ...")
+    _, m3, _ = timed_launches(lambda: ts.device_partition(labels, pay, num_classes=64, labels_out=lo,
+                                                          payload_out=po), 5, 2, torch)
+    ts.check_device_errors()
+    ll = lo.to(torch.int64)
+    okp = bool((ll[idx] <= ll[idx + 1]).all().item()) and \
+        bool((labels.to(torch.int64)[po[idx].to(torch.int64)] == ll[idx]).all().item())
     out = {"device_sort_keys": n, "device_sort_keys_payload_per_s": n / (m / 1e3),
            "device_sort_ms": m, "device_sort_sampled_check": "ok" if ok else "MISMATCH",
-           "torch_sort_stable_int32_per_s": n / (m2 / 1e3)}
-    del keys, pay, ko, po
+           "torch_sort_stable_int32_per_s": n / (m2 / 1e3),
+           "device_partition_labels_payload_per_s": n / (m3 / 1e3), "device_partition_ms": m3,
+           "device_partition_sampled_check": "ok" if okp else "MISMATCH"}
+    del keys, pay, ko, po, labels, lo
     torch.cuda.empty_cache()
     return out
 

@@ -100,7 +100,8 @@ enum {
 };
 
 /* Operation ids for ts_workspace_bytes */
-enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2, TS_OP_DEVICE_SORT = 3 };
+enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2, TS_OP_DEVICE_SORT = 3,
+       TS_OP_DEVICE_PARTITION = 4 };
 
 /*
  * tile_sort -- sorting (Sec. 1, "Problems of interest": sorting; Sec. 2, Lemma 1
@@ -187,6 +188,33 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels,
 ts_status ts_device_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t* payload_in,
                          uint32_t* payload_out, int32_t* perm_out, int64_t n, uint32_t flags,
                          void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * ts_device_partition -- stable w-way partition of one array of n labels (the whole
+ * array, not tiles): items grouped by label in ascending label order, input order kept
+ * within a label (Sec. 1: partitioning, and its use as the step of a quicksort with
+ * pivots).  One pass of ts_device_sort with the label as the digit: per-tile label
+ * counts, their prefix in label-major order, and the conflict-free split partition of
+ * every 4096-item tile storing each label block at its place in the array.
+ *   labels_in / out     : uint32 [n] (device, must not alias); labels in
+ *                         [0, num_classes), 1 <= num_classes <= 64.
+ *   payload_in / out    : optional uint32 [n] moved with the labels (one word each).
+ *   perm_out            : optional int32 [n]: source index of every output slot; not
+ *                         together with a payload (TS_ERR_UNSUPPORTED).
+ *   n                   : 0 <= n < 2^31.
+ *   flags               : TS_FLAG_VALIDATE: a label >= num_classes sets the workspace
+ *                         error word (ts_check).  Unchecked, such a label is split on
+ *                         its low ceil(log2(num_classes)) bits; no access leaves the
+ *                         arrays either way.
+ *   workspace           : ts_workspace_bytes(TS_OP_DEVICE_PARTITION, flags, 1, n, n, 0)
+ *                         bytes (the tile count tables; no second copy of the data).
+ * Returns TS_ERR_INVALID for NULL or aliasing arrays or a bad num_classes,
+ * TS_ERR_WORKSPACE for a short workspace; the work is enqueued on `stream`.
+ */
+ts_status ts_device_partition(const uint32_t* labels_in, uint32_t* labels_out,
+                              const uint32_t* payload_in, uint32_t* payload_out, int32_t* perm_out,
+                              int64_t n, uint32_t num_classes, uint32_t flags, void* workspace,
+                              size_t workspace_bytes, void* stream);
 
 /* Bytes of workspace a call of operation `op` (TS_OP_*) with these flags and sizes
    needs (never 0).  total_len is the number of items (tile_offsets[num_tiles]). */

@@ -18,11 +18,12 @@ TS_FLAG_VALIDATE = 2
 TS_FLAG_PI_U16 = 4
 TS_FLAG_INV_U16 = 8
 SCHED = {"auto": 0, "split": 1, "thm2": 2, "bitonic": 3, "merge": 4, "naive": 15}
-TS_OP_SORT, TS_OP_PARTITION, TS_OP_PERMUTE, TS_OP_DEVICE_SORT = 0, 1, 2, 3
+TS_OP_SORT, TS_OP_PARTITION, TS_OP_PERMUTE, TS_OP_DEVICE_SORT, TS_OP_DEVICE_PARTITION = 0, 1, 2, 3, 4
 
 # Every symbol include/tilesort.h declares.
 EXPORTS = (
-    "tile_sort", "tile_partition", "tile_permute", "ts_device_sort", "ts_workspace_bytes", "ts_workspace_init",
+    "tile_sort", "tile_partition", "tile_permute", "ts_device_sort", "ts_device_partition",
+    "ts_workspace_bytes", "ts_workspace_init",
     "ts_check", "ts_last_error", "ts_version", "ts_copy", "ts_lds_probe", "ts_tune",
 )
 
@@ -55,7 +56,8 @@ def load() -> ctypes.CDLL:
     lib.tile_partition.argtypes = [P, P, P, P, U32, I64, I64, U32, P, P, I64, I64, U32, P, SZ, P]
     lib.tile_permute.argtypes = [P, P, U32, I64, I64, P, U32, P, P, I64, I64, U32, P, SZ, P]
     lib.ts_device_sort.argtypes = [P, P, P, P, P, I64, U32, P, SZ, P]
-    for f in ("tile_sort", "tile_partition", "tile_permute", "ts_device_sort"):
+    lib.ts_device_partition.argtypes = [P, P, P, P, P, I64, U32, U32, P, SZ, P]
+    for f in ("tile_sort", "tile_partition", "tile_permute", "ts_device_sort", "ts_device_partition"):
         getattr(lib, f).restype = S
     lib.ts_workspace_bytes.argtypes = [ctypes.c_int, U32, I64, I64, I64, U32]
     lib.ts_workspace_bytes.restype = SZ

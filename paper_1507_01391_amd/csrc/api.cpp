@@ -137,6 +137,8 @@ size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t tot
         return kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
     if (op == TS_OP_DEVICE_SORT)
         return total_len > 0 ? ts::device_sort_layout(total_len, channels > 0).total : kWorkspaceBytes;
+    if (op == TS_OP_DEVICE_PARTITION)
+        return total_len > 0 ? ts::device_sort_layout(total_len, false, false).total : kWorkspaceBytes;
     if (op != TS_OP_SORT || num_tiles <= 0 || total_len < 0) return kWorkspaceBytes;
     const int sched = resolve_sort_sched(flags, max_tile_len, num_tiles);
     if (sched == TS_SCHED_MERGE) return ts::merge_layout(num_tiles, total_len, max_tile_len).total;
@@ -473,6 +475,44 @@ ts_status ts_device_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint
     d.f32 = (flags & TS_FLAG_F32_ORDERED) ? 1u : 0u;
     d.err = (uint32_t*)workspace;
     return hip_status(ts::launch_device_sort(d, workspace, (hipStream_t)stream), "ts_device_sort launch");
+}
+
+ts_status ts_device_partition(const uint32_t* labels_in, uint32_t* labels_out,
+                              const uint32_t* payload_in, uint32_t* payload_out, int32_t* perm_out,
+                              int64_t n, uint32_t num_classes, uint32_t flags, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+    if (n < 0) return fail(TS_ERR_INVALID, "ts_device_partition: n < 0");
+    if (n > INT32_MAX) return fail(TS_ERR_UNSUPPORTED, "ts_device_partition: n >= 2^31");
+    if (num_classes < 1 || num_classes > 64)
+        return fail(TS_ERR_INVALID, "ts_device_partition: num_classes must be in [1, 64]");
+    if (workspace == nullptr) return fail(TS_ERR_WORKSPACE, "workspace is NULL");
+    if (n == 0) return TS_OK;
+    if (labels_in == nullptr || labels_out == nullptr)
+        return fail(TS_ERR_INVALID, "ts_device_partition: labels are NULL");
+    if (labels_in == labels_out) return fail(TS_ERR_INVALID, "ts_device_partition: labels_in and labels_out alias");
+    if ((payload_in == nullptr) != (payload_out == nullptr))
+        return fail(TS_ERR_INVALID, "ts_device_partition: payload_in and payload_out must both be given");
+    if (payload_in != nullptr && payload_in == payload_out)
+        return fail(TS_ERR_INVALID, "ts_device_partition: payload_in and payload_out alias");
+    if (payload_in != nullptr && perm_out != nullptr)
+        return fail(TS_ERR_UNSUPPORTED, "ts_device_partition: a payload and perm_out together");
+    const size_t need = ts::device_sort_layout(n, false, false).total;
+    if (workspace_bytes < need)
+        return fail(TS_ERR_WORKSPACE, "ts_device_partition needs %zu workspace bytes (got %zu)", need,
+                    workspace_bytes);
+    int nbits = 0;
+    while ((1u << nbits) < num_classes) ++nbits;
+    ts::DeviceSortArgs d{};
+    d.keys_in = labels_in;
+    d.keys_out = labels_out;
+    d.pay_in = payload_in;
+    d.pay_out = payload_out;
+    d.perm_out = perm_out;
+    d.n = n;
+    d.err = (uint32_t*)workspace;
+    return hip_status(ts::launch_device_partition(d, nbits, num_classes, (flags & TS_FLAG_VALIDATE) != 0,
+                                                  workspace, (hipStream_t)stream),
+                      "ts_device_partition launch");
 }
 
 ts_status ts_copy(const void* src, void* dst, size_t bytes, void* stream) {

@@ -101,14 +101,17 @@ TS_DEV uint32_t row_prefix_sum(uint32_t v) {
     }
 }
 
-// Inclusive prefix sum across the 64 lanes of a wavefront.
+// Inclusive prefix sum across the 64 lanes of a wavefront (all lanes active), in DPP:
+// a prefix sum inside each row of 16 lanes, then lane 15 of rows 0 and 2 is added to
+// rows 1 and 3 (row_bcast:15) and lane 31 to rows 2 and 3 (row_bcast:31).  Rows left
+// out by the row mask read 0 (`old`), so they add nothing.
 TS_DEV uint32_t wave_inclusive_scan_u32(uint32_t v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t u = (uint32_t)__shfl_up((int)v, d, 64);
-        if (lane >= d) v += u;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false); // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false); // row_bcast:31
     return v;
 }
 

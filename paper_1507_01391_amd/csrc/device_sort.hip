@@ -37,9 +37,11 @@ __global__ void radix_offsets_kernel(int64_t* offs, int64_t T, int64_t n) {
 // banks (word mod 32) differ inside each 32-lane half, so there are no bank conflicts.
 // Lane d then sums row d with 64-bit reads in the order skewed by d, so that the 32
 // lanes of a phase read 8-byte slots 32 d + ((k + d) mod 32): distinct modulo 32.
+// With `limit` > 0 (a device partition with validation), keys >= limit set ERR_BAD_LABEL.
 __global__ __launch_bounds__(64) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
                                                         int64_t T, int shift, int nbits, uint32_t f32,
-                                                        uint32_t* __restrict__ hist) {
+                                                        uint32_t* __restrict__ hist, uint32_t limit,
+                                                        uint32_t* __restrict__ err) {
     __shared__ uint64_t cnt[RADIX_DIGITS * 64 / 2];
     const int lane = lane_id();
     const int64_t t = xcd_contiguous(blockIdx.x, gridDim.x);  // grid = T, one tile each
@@ -54,12 +56,15 @@ __global__ __launch_bounds__(64) void radix_hist_kernel(const uint32_t* __restri
     wave_lds_fence();
     const uint32_t dmask = (1u << nbits) - 1u;
     uint32_t* words = (uint32_t*)cnt;
+    bool bad = false;
 #pragma unroll
     for (int j = 0; j < HIST_CPL; ++j) {
         const uint32_t i = (uint32_t)(64 * j + lane);
         const uint32_t key = f32 ? f32_to_ordered(k[j]) : k[j];
         if (i < len) atomicAdd(&words[((key >> shift) & dmask) * 64u + (uint32_t)lane], 1u);
+        bad |= limit != 0u && i < len && key >= limit;
     }
+    if (limit != 0u) flag_error(err, bad, ERR_BAD_LABEL);
     wave_lds_fence();
     uint32_t sum = 0;
 #pragma unroll
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_apply_kernel(const uint32_t
 
 }  // namespace
 
-DeviceSortLayout device_sort_layout(int64_t n, bool with_pay) {
+DeviceSortLayout device_sort_layout(int64_t n, bool with_pay, bool pingpong) {
     DeviceSortLayout L{};
     const int64_t T = (n + RADIX_TILE - 1) / RADIX_TILE;
     const int64_t m = (int64_t)RADIX_DIGITS * T;
@@ -159,9 +164,9 @@ DeviceSortLayout device_sort_layout(int64_t n, bool with_pay) {
     L.bsum = off;
     off += al((size_t)nb * 4);
     L.keys = off;
-    off += al((size_t)n * 4);
+    off += al(pingpong ? (size_t)n * 4 : 0);
     L.pay = off;
-    off += al(with_pay ? (size_t)n * 4 : 0);
+    off += al(pingpong && with_pay ? (size_t)n * 4 : 0);
     L.total = off;
     return L;
 }
@@ -196,7 +201,8 @@ hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s) 
         uint32_t* pout = carry ? (to_ws ? tp : out_pay) : nullptr;
         const uint32_t f32_in = (p == 0) ? d.f32 : 0u;
         hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)T), dim3(64), 0, s, kin, n, T,
-                           RADIX_BITS * p, std::min(RADIX_BITS, 32 - RADIX_BITS * p), f32_in, hist);
+                           RADIX_BITS * p, std::min(RADIX_BITS, 32 - RADIX_BITS * p), f32_in, hist, 0u,
+                           d.err);
         hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum);
         hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
         hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum, goff);
@@ -220,6 +226,43 @@ hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s) 
         e = launch_radix_pass(r, s);
     }
     return e;
+}
+
+hipError_t launch_device_partition(const DeviceSortArgs& d, int nbits, uint32_t num_classes,
+                                   bool validate, void* ws, hipStream_t s) {
+    const int64_t n = d.n;
+    if (n == 0) return hipSuccess;
+    const DeviceSortLayout L = device_sort_layout(n, false, false);
+    char* w = (char*)ws;
+    int64_t* offs = (int64_t*)(w + L.offsets);
+    uint32_t* hist = (uint32_t*)(w + L.hist);
+    uint32_t* goff = (uint32_t*)(w + L.goff);
+    uint32_t* bsum = (uint32_t*)(w + L.bsum);
+    const int64_t T = (n + RADIX_TILE - 1) / RADIX_TILE;
+    const int64_t m = (int64_t)RADIX_DIGITS * T;
+    const int64_t nb = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    hipLaunchKernelGGL(radix_offsets_kernel, dim3((unsigned)((T + 1 + 255) / 256)), dim3(256), 0, s, offs, T, n);
+    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)T), dim3(64), 0, s, d.keys_in, n, T, 0, nbits, 0u, hist,
+                       validate ? num_classes : 0u, d.err);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum);
+    hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum, goff);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    RadixPass r{};
+    r.keys_in = d.keys_in;
+    r.keys_out = d.keys_out;
+    r.pay_in = d.pay_in;  // NULL: the kernel carries the index (for perm_out)
+    r.pay_out = d.pay_out ? d.pay_out : (uint32_t*)d.perm_out;
+    r.offsets = offs;
+    r.num_tiles = T;
+    r.shift = 0;
+    r.nbits = nbits;
+    r.hist = hist;
+    r.goff = goff;
+    r.n_total = n;
+    r.err = d.err;
+    return launch_radix_pass(r, s);
 }
 
 }  // namespace ts

@@ -98,8 +98,14 @@ struct DeviceSortArgs {
 struct DeviceSortLayout {
     size_t offsets, hist, goff, bsum, keys, pay, total;
 };
-DeviceSortLayout device_sort_layout(int64_t n, bool with_pay);
+// with_pay: a payload word travels; pingpong: room for a second copy of the data (the
+// sort's passes alternate between it and the output; a single partition pass needs none)
+DeviceSortLayout device_sort_layout(int64_t n, bool with_pay, bool pingpong = true);
 hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s);
+// One pass on the low `nbits` bits of the labels; with `validate`, labels >= num_classes
+// set ERR_BAD_LABEL.
+hipError_t launch_device_partition(const DeviceSortArgs& d, int nbits, uint32_t num_classes,
+                                   bool validate, void* ws, hipStream_t s);
 
 // Sorting tiles of uneven length by pieces and merges (merge.hip).
 constexpr int MERGE_PIECE = 4096;          // keys per wavefront work item

@@ -257,11 +257,13 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
             }
             const int ls = (int)opaque((uint32_t)lane);
             const uint32_t dmask = (1u << a.nbits) - 1u;
+            const uint32_t ntot = (uint32_t)a.n_total;
+            uint32_t dst[CPW];
+            bool bad = false;  // counts that disagree with the tile: not stored, recorded
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
-                const int v = 64 * (w * CPW + j) + ls;
-                const uint32_t h = hi32(e[j]);
-                const uint32_t d = (h >> a.shift) & dmask;
+                const uint32_t v = (uint32_t)(64 * (w * CPW + j) + ls);
+                const uint32_t d = (hi32(e[j]) >> a.shift) & dmask;
                 const int src = (int)((d & 63u) * 4u);
                 uint32_t dl = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)delta[0]);
 #pragma unroll
@@ -269,15 +271,36 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
                     const uint32_t x = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)delta[q]);
                     dl = ((d >> 6) == (uint32_t)q) ? x : dl;
                 }
-                const int64_t dst = (int64_t)(dl + (uint32_t)v);
-                if (v < n && dst < a.n_total) {
-                    a.keys_out[dst] = a.f32_out ? ordered_to_f32(h) : h;
-                    if (a.pay_out) a.pay_out[dst] = lo32(e[j]);
-                }
-                // counts that disagree with the tile would send a key past the end: not
-                // stored, recorded instead
-                if (a.validate) flag_error(a.err, v < n && dst >= a.n_total, ERR_BAD_OFFSETS);
+                const bool real = v < (uint32_t)n;
+                const uint32_t g = dl + v;
+                bad |= real && g >= ntot;
+                dst[j] = (real && g < ntot) ? g : ntot;  // ntot: past the end, dropped
             }
+            if (a.n_total <= (int64_t)0x3FFFFFFF) {
+                // byte offsets fit in 32 bits: buffer stores over the whole output, the
+                // hardware range check drops the ones at ntot
+                const rsrc_t rk = buffer_rsrc(a.keys_out, ntot * 4u);
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) {
+                    const uint32_t h = hi32(e[j]);
+                    buffer_store<false>(rk, dst[j] * 4u, a.f32_out ? ordered_to_f32(h) : h);
+                }
+                if (a.pay_out) {
+                    const rsrc_t rp = buffer_rsrc(a.pay_out, ntot * 4u);
+#pragma unroll
+                    for (int j = 0; j < CPW; ++j) buffer_store<false>(rp, dst[j] * 4u, lo32(e[j]));
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) {
+                    if (dst[j] < ntot) {
+                        const uint32_t h = hi32(e[j]);
+                        a.keys_out[dst[j]] = a.f32_out ? ordered_to_f32(h) : h;
+                        if (a.pay_out) a.pay_out[dst[j]] = lo32(e[j]);
+                    }
+                }
+            }
+            if (a.validate) flag_error(a.err, bad, ERR_BAD_OFFSETS);
         } else
         // ---- store in order (coalesced: column k covers items 64k .. 64k+63), one
         //      uniform branch per output; stores past the end of the tile are dropped by

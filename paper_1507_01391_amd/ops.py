@@ -224,6 +224,38 @@ def device_sort(keys: torch.Tensor, payload: Optional[torch.Tensor] = None, want
     return keys_out, payload_out, perm_out
 
 
+def device_partition(labels: torch.Tensor, payload: Optional[torch.Tensor] = None, num_classes: int = 64,
+                     want_perm: bool = False, validate: bool = False,
+                     labels_out: Optional[torch.Tensor] = None, payload_out: Optional[torch.Tensor] = None,
+                     perm_out: Optional[torch.Tensor] = None):
+    """Stable num_classes-way partition of one whole array of labels (ts_device_partition):
+    one pass of the device-wide sort with the label as the digit.  ``payload`` is an
+    optional [N] 32-bit tensor moved with the labels; ``want_perm`` returns the source
+    index of every output slot (not together with a payload).  With ``validate`` a label
+    >= num_classes is reported by check_device_errors().  Returns (labels_out,
+    payload_out or None, perm or None)."""
+    labels = _as_words(labels, "labels")
+    assert labels.dim() == 1
+    n = labels.shape[0]
+    dev = labels.device
+    if payload is not None:
+        payload = _as_words(payload, "payload")
+        assert payload.shape == labels.shape, "one payload word per label"
+        if payload_out is None:
+            payload_out = torch.empty_like(payload)
+    if labels_out is None:
+        labels_out = torch.empty_like(labels)
+    if want_perm and perm_out is None:
+        perm_out = torch.empty(n, dtype=torch.int32, device=dev)
+    flags = _lib.TS_FLAG_VALIDATE if validate else 0
+    lib = _lib.load()
+    ws = workspace(dev, lib.ts_workspace_bytes(_lib.TS_OP_DEVICE_PARTITION, flags, 1, n, n, 0))
+    _lib.check(lib.ts_device_partition(_ptr(labels), _ptr(labels_out), _ptr(payload), _ptr(payload_out),
+                                       _ptr(perm_out), n, num_classes, flags, _ptr(ws), ws.numel() * 4,
+                                       _stream(dev)))
+    return labels_out, payload_out, perm_out
+
+
 def copy(src: torch.Tensor, dst: torch.Tensor) -> None:
     """HBM reference copy (16-byte vector loads and stores)."""
     assert src.is_cuda and dst.is_cuda and src.numel() * src.element_size() <= dst.numel() * dst.element_size()

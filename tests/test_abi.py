@@ -146,3 +146,24 @@ def test_device_sort_argument_validation(lib):
     assert lib.ts_device_sort(keys, out, None, None, perm, 100, 0, ws, need - 1, None) == 4  # workspace
     assert lib.ts_device_sort(keys, out, None, None, None, 0, 0, ws, 0, None) == 0           # empty: nothing to do
     assert lib.ts_device_sort(keys, out, None, None, None, 100, 0, None, big, None) == 4
+
+
+def test_device_partition_argument_validation(lib):
+    P = ctypes.c_void_p
+    lab, out, pay, pout, perm, ws = P(0x1000), P(0x2000), P(0x3000), P(0x4000), P(0x5000), P(0x8000)
+    big = 1 << 40
+    f = lib.ts_device_partition
+    assert f(lab, out, None, None, None, -1, 64, 0, ws, big, None) == 1
+    assert f(lab, out, None, None, None, 1 << 31, 64, 0, ws, big, None) == 2
+    assert f(lab, out, None, None, None, 100, 0, 0, ws, big, None) == 1           # no classes
+    assert f(lab, out, None, None, None, 100, 65, 0, ws, big, None) == 1          # more than w
+    assert f(lab, lab, None, None, None, 100, 64, 0, ws, big, None) == 1          # alias
+    assert f(None, out, None, None, None, 100, 64, 0, ws, big, None) == 1
+    assert f(lab, out, pay, None, None, 100, 64, 0, ws, big, None) == 1           # half a payload
+    assert f(lab, out, pay, pay, None, 100, 64, 0, ws, big, None) == 1            # payload alias
+    assert f(lab, out, pay, pout, perm, 100, 64, 0, ws, big, None) == 2           # payload + perm
+    need = lib.ts_workspace_bytes(4, 0, 1, 100, 100, 0)
+    assert 256 <= need < lib.ts_workspace_bytes(3, 0, 1, 100, 100, 0)              # no second data copy
+    assert f(lab, out, None, None, perm, 100, 64, 0, ws, need - 1, None) == 4     # workspace
+    assert f(lab, out, None, None, None, 0, 64, 0, ws, 0, None) == 0              # empty
+    assert f(lab, out, None, None, None, 100, 64, 0, None, big, None) == 4

@@ -70,3 +70,52 @@ def test_large_against_numpy(ts):
     order = np.argsort(keys, kind="stable")
     assert np.array_equal(perm.cpu().numpy(), order.astype(np.int32))
     assert np.array_equal(k.cpu().numpy().view(np.uint32), keys[order])
+
+
+# ------------------------------------------------------------- device-wide partition
+
+
+@pytest.mark.parametrize("num_classes", [1, 2, 17, 64])
+@pytest.mark.parametrize("n", [1, 4095, 4097, 100003, (1 << 20) + 77])
+def test_partition_payload(ts, oracle, n, num_classes):
+    rng = np.random.default_rng(n + num_classes)
+    lab = rng.integers(0, num_classes, size=n, dtype=np.uint32)
+    pay = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    lo, po, _ = ts.device_partition(dev(lab), dev(pay), num_classes=num_classes, validate=True)
+    ts.check_device_errors()
+    wl, wp, _ = oracle.tile_partition(lab, pay, num_classes=num_classes, nthreads=8)
+    assert np.array_equal(lo.cpu().numpy().view(np.uint32), wl)
+    assert np.array_equal(po.cpu().numpy().view(np.uint32), wp)
+
+
+@pytest.mark.parametrize("shape", ["equal_counts", "one_class", "skewed"])
+def test_partition_perm(ts, oracle, shape):
+    """The permutation pins stability: inside a label, sources ascend."""
+    n = 64 * 4096 + 1000
+    rng = np.random.default_rng(11)
+    if shape == "equal_counts":      # the C2 label mix over the whole array
+        lab = rng.permutation(np.arange(n, dtype=np.uint32) % 64)
+    elif shape == "one_class":
+        lab = np.full(n, 9, dtype=np.uint32)
+    else:
+        lab = np.minimum(rng.zipf(1.3, size=n) - 1, 63).astype(np.uint32)
+    lo, _, perm = ts.device_partition(dev(lab), want_perm=True)
+    ts.check_device_errors()
+    wl, _, wperm = oracle.tile_partition(lab, nthreads=8)
+    assert np.array_equal(lo.cpu().numpy().view(np.uint32), wl)
+    assert np.array_equal(perm.cpu().numpy(), wperm)
+
+
+def test_partition_reports_bad_labels(ts):
+    """A label >= num_classes is reported (validate) and every output stays a
+    permutation of the input: no item is lost or written out of bounds."""
+    n = 3 * 4096 + 5
+    lab = (np.arange(n, dtype=np.uint32) % 10)
+    lab[4100] = 12                                   # outside [0, 10)
+    lo, _, perm = ts.device_partition(dev(lab), num_classes=10, want_perm=True, validate=True)
+    from paper_1507_01391_amd._lib import TileSortError
+    with pytest.raises(TileSortError):
+        ts.check_device_errors()
+    p = perm.cpu().numpy()
+    assert np.array_equal(np.sort(p), np.arange(n, dtype=np.int32))
+    assert np.array_equal(lo.cpu().numpy().view(np.uint32), lab[p])
