@@ -377,10 +377,13 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
             return fail(TS_ERR_WORKSPACE, "tile_sort: payload without perm_out needs %zu workspace bytes", need);
         a.perm_out = (int32_t*)((char*)workspace + kWorkspaceBytes);
     }
+    // A small batch sorted by the split schedule gathers the payload in the sort
+    // kernel's store (a global gather inside each tile), sparing the second launch.
+    a.fuse_pay = (channels > 0 && sched == TS_SCHED_SPLIT && num_tiles <= g_sort_small_batch) ? 1u : 0u;
     hipError_t e = (sched == TS_SCHED_NAIVE) ? ts::launch_sort_naive(a, max_tile_len, s)
                                              : ts::launch_sort(a, max_tile_len, sched, s);
     if (e != hipSuccess) return hip_status(e, "tile_sort launch");
-    if (channels > 0) {
+    if (channels > 0 && !a.fuse_pay) {
         // the payload is not part of the composite: gather it by the permutation
         // (a conflict-free routing per tile), or by a direct LDS gather for the baseline
         ts::PermuteArgs p{};

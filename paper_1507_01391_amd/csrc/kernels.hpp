@@ -58,6 +58,7 @@ struct SortArgs {
     int64_t num_tiles;
     uint32_t f32;       // nonzero: keys are binary32 patterns
     uint32_t* err;
+    uint32_t fuse_pay;  // split schedule: gather the payload in the sort kernel's store
 };
 
 // One pass of the device-wide radix sort (device_sort.hip): tiles of 4096 items split

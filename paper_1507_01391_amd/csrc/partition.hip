@@ -60,6 +60,9 @@ struct SplitArgs {
     const uint32_t* hist;       // [RADIX_DIGITS][num_tiles] digit counts of every tile
     const uint32_t* goff;       // [RADIX_DIGITS][num_tiles] exclusive prefix of hist in that order
     int64_t n_total;            // length of the whole array (destinations are below it)
+    // MODE 1 only: payload words gathered from global memory at the store (out[v] =
+    // in[position of rank v]), for small batches where a second launch costs more
+    PayloadRef gpay;
 };
 
 template <int CPW>
@@ -338,6 +341,26 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
 #pragma unroll
                 for (int j = 0; j < CPW; ++j) buffer_store<NTS>(r, off + 256u * j, v[j]);
             }
+            if (MODE == 1 && a.gpay.out != nullptr) {
+                // rank v takes the words of its source position; both stay inside the tile
+                const int64_t es = a.gpay.es, cs = a.gpay.cs;
+                for (uint32_t c = 0; c < a.gpay.channels; ++c) {
+                    const uint32_t* src = a.gpay.in + o * es + (int64_t)c * cs;
+                    uint32_t* dst = a.gpay.out + o * es + (int64_t)c * cs;
+                    // ranks below n hold real items, whose positions are below n; the
+                    // padding ranks load and store nothing
+#pragma unroll
+                    for (int j = 0; j < CPW; ++j) {
+                        const int r = 64 * (w * CPW + j) + ls;
+                        v[j] = (r < n) ? src[(int64_t)lo32(e[j]) * es] : 0u;
+                    }
+#pragma unroll
+                    for (int j = 0; j < CPW; ++j) {
+                        const int r = 64 * (w * CPW + j) + ls;
+                        if (r < n) dst[(int64_t)r * es] = v[j];
+                    }
+                }
+            }
         }
         if (!PREFETCH) issue_tile_load<CPW, CAP, NTL>(a, offs, t + gridDim.x, w, lane, L);
     }
@@ -450,9 +473,13 @@ hipError_t launch_sort_split(const SortArgs& q, int64_t max_len, hipStream_t s) 
     a.nbits = 32;
     a.f32 = q.f32;
     a.err = q.err;
+    if (q.fuse_pay) a.gpay = q.pay;
     const int64_t* o = q.offsets;
     if (max_len <= 1024) return launch_split_shaped<4, 1024, 0, 1>(a, o, s);
     if (max_len <= 2048) return launch_split_shaped<4, 2048, 0, 1>(a, o, s);
+    // up to about one tile per CU the sort is latency-bound: 16 waves halve each wave's
+    // columns per pass
+    if (max_len <= 4096 && q.num_tiles <= 256) return launch_split_shaped<16, 4096, 0, 1>(a, o, s);
     if (max_len <= 4096) return launch_split_shaped<8, 4096, 0, 1>(a, o, s);
     if (max_len <= 8192) return launch_split_shaped<8, 8192, 0, 1>(a, o, s);
     return launch_split_shaped<16, 16384, 0, 1>(a, o, s);

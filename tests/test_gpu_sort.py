@@ -220,3 +220,24 @@ def test_64bit_payload(ts, oracle, schedule):
     assert np.array_equal(k.cpu().numpy().view(np.uint32), wk)
     assert np.array_equal(perm.cpu().numpy(), wperm)
     assert np.array_equal(p.cpu().numpy().view(np.uint32).reshape(n, 2).T, wp)
+
+
+@pytest.mark.parametrize("num_tiles", [3, 1024, 1100])
+def test_split_payload_fused_and_routed(ts, oracle, num_tiles):
+    """The split schedule gathers a small batch's payload in the sort kernel (up to
+    sort_small_batch = 1024 tiles) and a larger batch's with the router; both agree with
+    the oracle on a 3-channel planar payload."""
+    from tests.gpu_util import dev
+    rng = np.random.default_rng(num_tiles)
+    sizes = rng.integers(0, 300, size=num_tiles)
+    sizes[0] = 4096
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    keys = rng.integers(0, 50, size=n, dtype=np.uint32)
+    pay = rng.integers(0, 2**32, size=(3, n), dtype=np.uint32)
+    k, p, perm = ts.tile_sort(dev(keys), dev(pay), dev(off), max_tile_len=4096, schedule="split")
+    ts.check_device_errors()
+    wk, wp, wperm = oracle.tile_sort(keys, pay, off, nthreads=8)
+    assert np.array_equal(k.cpu().numpy().view(np.uint32), wk)
+    assert np.array_equal(perm.cpu().numpy(), wperm)
+    assert np.array_equal(p.cpu().numpy().view(np.uint32), wp)
