@@ -136,9 +136,12 @@ size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t tot
         (sched_of(flags) == TS_SCHED_THM2 || sched_of(flags) == TS_SCHED_BITONIC))
         return kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
     if (op == TS_OP_DEVICE_SORT)
-        return total_len > 0 ? ts::device_sort_layout(total_len, channels > 0).total : kWorkspaceBytes;
+        return total_len > 0 ? ts::device_sort_layout(total_len, ts::radix_tile(channels > 0), channels > 0).total
+                             : kWorkspaceBytes;
     if (op == TS_OP_DEVICE_PARTITION)
-        return total_len > 0 ? ts::device_sort_layout(total_len, false, false).total : kWorkspaceBytes;
+        // the count tables of the smaller tiles: enough for either tile size
+        return total_len > 0 ? ts::device_sort_layout(total_len, ts::RADIX_TILE_KEYS, false, false).total
+                             : kWorkspaceBytes;
     if (op != TS_OP_SORT || num_tiles <= 0 || total_len < 0) return kWorkspaceBytes;
     const int sched = resolve_sort_sched(flags, max_tile_len, num_tiles);
     if (sched == TS_SCHED_MERGE) return ts::merge_layout(num_tiles, total_len, max_tile_len).total;
@@ -465,7 +468,7 @@ ts_status ts_device_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint
     if (payload_in != nullptr && perm_out != nullptr)
         return fail(TS_ERR_UNSUPPORTED, "ts_device_sort: a payload and perm_out together");
     const bool carry = payload_in != nullptr || perm_out != nullptr;
-    const size_t need = ts::device_sort_layout(n, carry).total;
+    const size_t need = ts::device_sort_layout(n, ts::radix_tile(carry), carry).total;
     if (workspace_bytes < need)
         return fail(TS_ERR_WORKSPACE, "ts_device_sort needs %zu workspace bytes (got %zu)", need, workspace_bytes);
     ts::DeviceSortArgs d{};
@@ -499,7 +502,7 @@ ts_status ts_device_partition(const uint32_t* labels_in, uint32_t* labels_out,
         return fail(TS_ERR_INVALID, "ts_device_partition: payload_in and payload_out alias");
     if (payload_in != nullptr && perm_out != nullptr)
         return fail(TS_ERR_UNSUPPORTED, "ts_device_partition: a payload and perm_out together");
-    const size_t need = ts::device_sort_layout(n, false, false).total;
+    const size_t need = ts::device_sort_layout(n, ts::RADIX_TILE_KEYS, false, false).total;
     if (workspace_bytes < need)
         return fail(TS_ERR_WORKSPACE, "ts_device_partition needs %zu workspace bytes (got %zu)", need,
                     workspace_bytes);

@@ -22,55 +22,71 @@ namespace ts {
 
 namespace {
 
-constexpr int HIST_CPL = RADIX_TILE / 64;  // keys per lane: one wavefront per tile
+constexpr int HIST_CPL = 64;  // keys per lane: one wavefront per 4096 keys of a tile
 static_assert(RADIX_DIGITS == 64, "lane d sums the counts of digit d");
 
 // offs[t] = min(t * 4096, n) for t = 0 .. T.
-__global__ void radix_offsets_kernel(int64_t* offs, int64_t T, int64_t n) {
+__global__ void radix_offsets_kernel(int64_t* offs, int64_t T, int64_t n, int tile) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t <= T) offs[t] = std::min<int64_t>(t * RADIX_TILE, n);
+    if (t <= T) offs[t] = std::min<int64_t>(t * tile, n);
 }
 
 // hist[d][t] = number of keys of tile t whose digit is d (digits >= 2^nbits: 0).  One
-// wavefront per tile.  Lane l counts its 64 keys into a column of its own of an LDS
-// table (word 64 d + l): the 64 adds of one instruction hit 64 distinct words whose
-// banks (word mod 32) differ inside each 32-lane half, so there are no bank conflicts.
-// Lane d then sums row d with 64-bit reads in the order skewed by d, so that the 32
-// lanes of a phase read 8-byte slots 32 d + ((k + d) mod 32): distinct modulo 32.
+// wavefront per 4096 keys of the tile.  Lane l counts its 64 keys into a column of its
+// own of its wave's LDS table (word 64 d + l): the 64 adds of one instruction hit 64
+// distinct words whose banks (word mod 32) differ inside each 32-lane half, so there are
+// no bank conflicts.  Lane d then sums row d with 64-bit reads in the order skewed by d,
+// so that the 32 lanes of a phase read 8-byte slots 32 d + ((k + d) mod 32): distinct
+// modulo 32; the waves' row sums are added through LDS, one word per lane.
 // With `limit` > 0 (a device partition with validation), keys >= limit set ERR_BAD_LABEL.
-__global__ __launch_bounds__(64) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
-                                                        int64_t T, int shift, int nbits, uint32_t f32,
-                                                        uint32_t* __restrict__ hist, uint32_t limit,
-                                                        uint32_t* __restrict__ err) {
-    __shared__ uint64_t cnt[RADIX_DIGITS * 64 / 2];
+template <int HIST_W>
+__global__ __launch_bounds__(64 * HIST_W) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
+                                                                 int64_t T, int shift, int nbits, uint32_t f32,
+                                                                 uint32_t* __restrict__ hist, uint32_t limit,
+                                                                 uint32_t* __restrict__ err) {
+    __shared__ uint64_t cnt[HIST_W][RADIX_DIGITS * 64 / 2];
+    __shared__ uint32_t part[HIST_W][64];
     const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t t = xcd_contiguous(blockIdx.x, gridDim.x);  // grid = T, one tile each
-    const int64_t o = t * RADIX_TILE;
-    const uint32_t len = (uint32_t)std::min<int64_t>(RADIX_TILE, n - o);
+    const int64_t o = t * (4096 * HIST_W) + (int64_t)w * 4096;
+    const uint32_t len = (uint32_t)std::max<int64_t>(0, std::min<int64_t>(4096, n - o));
     uint32_t k[HIST_CPL];
-    buffer_load_columns<HIST_CPL, true>(buffer_rsrc(keys + o, len * 4u), (uint32_t)lane * 4u, k);
+    buffer_load_columns<HIST_CPL, true>(buffer_rsrc(keys + std::min<int64_t>(o, n), len * 4u),
+                                        (uint32_t)lane * 4u, k);
     // clear: lane l writes slot 64 r + l (words 128 r + 2l, +1): 16 lanes of a 64-bit
     // write phase cover 16 consecutive slots
 #pragma unroll
-    for (int r = 0; r < RADIX_DIGITS / 2; ++r) lds_store(cnt, (uint32_t)(64 * r + lane) * 8u, uint64_t(0));
+    for (int r = 0; r < RADIX_DIGITS / 2; ++r) lds_store(cnt[w], (uint32_t)(64 * r + lane) * 8u, uint64_t(0));
     wave_lds_fence();
+    if (limit != 0u) {  // labels of a validated device partition (keys are not binary32 there)
+        uint32_t bad = 0;
+#pragma unroll
+        for (int j = 0; j < HIST_CPL; ++j) bad |= (64u * j + (uint32_t)lane < len && k[j] >= limit) ? 1u : 0u;
+        flag_error(err, bad != 0u, ERR_BAD_LABEL);
+    }
     const uint32_t dmask = (1u << nbits) - 1u;
-    uint32_t* words = (uint32_t*)cnt;
-    bool bad = false;
+    uint32_t* words = (uint32_t*)cnt[w];
 #pragma unroll
     for (int j = 0; j < HIST_CPL; ++j) {
         const uint32_t i = (uint32_t)(64 * j + lane);
         const uint32_t key = f32 ? f32_to_ordered(k[j]) : k[j];
         if (i < len) atomicAdd(&words[((key >> shift) & dmask) * 64u + (uint32_t)lane], 1u);
-        bad |= limit != 0u && i < len && key >= limit;
     }
-    if (limit != 0u) flag_error(err, bad, ERR_BAD_LABEL);
     wave_lds_fence();
     uint32_t sum = 0;
 #pragma unroll
     for (int q = 0; q < 32; ++q) {
-        const uint64_t v = lds_load_u64_whole(cnt, (uint32_t)(32 * lane + ((q + lane) & 31)) * 8u);
+        const uint64_t v = lds_load_u64_whole(cnt[w], (uint32_t)(32 * lane + ((q + lane) & 31)) * 8u);
         sum += lo32(v) + hi32(v);
+    }
+    if constexpr (HIST_W > 1) {
+        part[w][lane] = sum;
+        __syncthreads();
+        if (w != 0) return;
+        sum = 0;
+#pragma unroll
+        for (int q = 0; q < HIST_W; ++q) sum += part[q][lane];
     }
     hist[(int64_t)lane * T + t] = sum;
 }
@@ -146,11 +162,21 @@ __global__ __launch_bounds__(SCAN_THREADS) void scan_apply_kernel(const uint32_t
     }
 }
 
+void launch_hist(int tile, const uint32_t* keys, int64_t n, int64_t T, int shift, int nbits, uint32_t f32,
+                 uint32_t* hist, uint32_t limit, uint32_t* err, hipStream_t s) {
+    if (tile == 8192)
+        hipLaunchKernelGGL(radix_hist_kernel<2>, dim3((unsigned)T), dim3(128), 0, s, keys, n, T, shift, nbits, f32,
+                           hist, limit, err);
+    else
+        hipLaunchKernelGGL(radix_hist_kernel<1>, dim3((unsigned)T), dim3(64), 0, s, keys, n, T, shift, nbits, f32,
+                           hist, limit, err);
+}
+
 }  // namespace
 
-DeviceSortLayout device_sort_layout(int64_t n, bool with_pay, bool pingpong) {
+DeviceSortLayout device_sort_layout(int64_t n, int tile, bool with_pay, bool pingpong) {
     DeviceSortLayout L{};
-    const int64_t T = (n + RADIX_TILE - 1) / RADIX_TILE;
+    const int64_t T = (n + tile - 1) / tile;
     const int64_t m = (int64_t)RADIX_DIGITS * T;
     const int64_t nb = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -175,7 +201,8 @@ hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s) 
     const int64_t n = d.n;
     if (n == 0) return hipSuccess;
     const bool carry = d.pay_in != nullptr || d.perm_out != nullptr;  // a payload word travels
-    const DeviceSortLayout L = device_sort_layout(n, carry);
+    const int tile = radix_tile(carry);
+    const DeviceSortLayout L = device_sort_layout(n, tile, carry);
     char* w = (char*)ws;
     int64_t* offs = (int64_t*)(w + L.offsets);
     uint32_t* hist = (uint32_t*)(w + L.hist);
@@ -183,12 +210,12 @@ hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s) 
     uint32_t* bsum = (uint32_t*)(w + L.bsum);
     uint32_t* tk = (uint32_t*)(w + L.keys);
     uint32_t* tp = carry ? (uint32_t*)(w + L.pay) : nullptr;
-    const int64_t T = (n + RADIX_TILE - 1) / RADIX_TILE;
+    const int64_t T = (n + tile - 1) / tile;
     const int64_t m = (int64_t)RADIX_DIGITS * T;
     const int64_t nb = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
     uint32_t* out_pay = d.pay_out ? d.pay_out : (uint32_t*)d.perm_out;  // final payload words
 
-    hipLaunchKernelGGL(radix_offsets_kernel, dim3((unsigned)((T + 1 + 255) / 256)), dim3(256), 0, s, offs, T, n);
+    hipLaunchKernelGGL(radix_offsets_kernel, dim3((unsigned)((T + 1 + 255) / 256)), dim3(256), 0, s, offs, T, n, tile);
     hipError_t e = hipGetLastError();
     // buffers: in -> ws, ws -> out, out -> ws, ..., ws -> out
     constexpr int kPasses = RADIX_PASSES;
@@ -200,9 +227,8 @@ hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s) 
         uint32_t* kout = to_ws ? tk : d.keys_out;
         uint32_t* pout = carry ? (to_ws ? tp : out_pay) : nullptr;
         const uint32_t f32_in = (p == 0) ? d.f32 : 0u;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)T), dim3(64), 0, s, kin, n, T,
-                           RADIX_BITS * p, std::min(RADIX_BITS, 32 - RADIX_BITS * p), f32_in, hist, 0u,
-                           d.err);
+        launch_hist(tile, kin, n, T, RADIX_BITS * p, std::min(RADIX_BITS, 32 - RADIX_BITS * p), f32_in, hist, 0u,
+                    d.err, s);
         hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum);
         hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
         hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum, goff);
@@ -223,6 +249,7 @@ hipError_t launch_device_sort(const DeviceSortArgs& d, void* ws, hipStream_t s) 
         r.goff = goff;
         r.n_total = n;
         r.err = d.err;
+        r.tile = tile;
         e = launch_radix_pass(r, s);
     }
     return e;
@@ -232,18 +259,19 @@ hipError_t launch_device_partition(const DeviceSortArgs& d, int nbits, uint32_t 
                                    bool validate, void* ws, hipStream_t s) {
     const int64_t n = d.n;
     if (n == 0) return hipSuccess;
-    const DeviceSortLayout L = device_sort_layout(n, false, false);
+    const bool carry = d.pay_in != nullptr || d.perm_out != nullptr;
+    const int tile = radix_tile(carry);
+    const DeviceSortLayout L = device_sort_layout(n, tile, carry, false);
     char* w = (char*)ws;
     int64_t* offs = (int64_t*)(w + L.offsets);
     uint32_t* hist = (uint32_t*)(w + L.hist);
     uint32_t* goff = (uint32_t*)(w + L.goff);
     uint32_t* bsum = (uint32_t*)(w + L.bsum);
-    const int64_t T = (n + RADIX_TILE - 1) / RADIX_TILE;
+    const int64_t T = (n + tile - 1) / tile;
     const int64_t m = (int64_t)RADIX_DIGITS * T;
     const int64_t nb = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    hipLaunchKernelGGL(radix_offsets_kernel, dim3((unsigned)((T + 1 + 255) / 256)), dim3(256), 0, s, offs, T, n);
-    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)T), dim3(64), 0, s, d.keys_in, n, T, 0, nbits, 0u, hist,
-                       validate ? num_classes : 0u, d.err);
+    hipLaunchKernelGGL(radix_offsets_kernel, dim3((unsigned)((T + 1 + 255) / 256)), dim3(256), 0, s, offs, T, n, tile);
+    launch_hist(tile, d.keys_in, n, T, 0, nbits, 0u, hist, validate ? num_classes : 0u, d.err, s);
     hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum);
     hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
     hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, hist, m, bsum, goff);
@@ -262,6 +290,7 @@ hipError_t launch_device_partition(const DeviceSortArgs& d, int nbits, uint32_t 
     r.goff = goff;
     r.n_total = n;
     r.err = d.err;
+    r.tile = tile;
     return launch_radix_pass(r, s);
 }
 

@@ -459,7 +459,8 @@ hipError_t launch_radix_pass(const RadixPass& r, hipStream_t s) {
     a.goff = r.goff;
     a.n_total = r.n_total;
     a.validate = 1;
-    static_assert(RADIX_TILE == 4096, "the pass kernel holds 4096-item tiles");
+    static_assert(RADIX_TILE_KEYS == 4096 && RADIX_TILE_PAY == 8192, "the pass kernel's tile sizes");
+    if (r.tile == RADIX_TILE_PAY) return launch_split<16, 8192, 8, 2, 0, 1, true>(a, r.offsets, s);
     return launch_split<8, 4096, 8, 2, 0, 1, true>(a, r.offsets, s);
 }
 
