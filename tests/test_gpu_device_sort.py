@@ -119,3 +119,27 @@ def test_partition_reports_bad_labels(ts):
     p = perm.cpu().numpy()
     assert np.array_equal(np.sort(p), np.arange(n, dtype=np.int32))
     assert np.array_equal(lo.cpu().numpy().view(np.uint32), lab[p])
+
+
+@pytest.mark.parametrize("n", [8191, 8192, 8193, 16384, 3 * 8192 + 4095])
+def test_payload_tile_edges(ts, oracle, n):
+    """Lengths around the 8192-item tiles that the passes use when a payload travels."""
+    rng = np.random.default_rng(n + 1)
+    keys = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    pay = np.arange(n, dtype=np.uint32) ^ np.uint32(0xA5A5A5A5)
+    k, p, _ = ts.device_sort(dev(keys), dev(pay))
+    ts.check_device_errors()
+    wk, wp, _ = oracle.tile_sort(keys, pay, nthreads=8)
+    assert np.array_equal(k.cpu().numpy().view(np.uint32), wk)
+    assert np.array_equal(p.cpu().numpy().view(np.uint32), wp)
+
+
+@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 8193, 65537])
+def test_keys_only_tile_edges(ts, n):
+    """Keys alone take 4096-item tiles; ties and the top digit (2 bits) included."""
+    rng = np.random.default_rng(n + 2)
+    keys = (rng.integers(0, 8, size=n, dtype=np.uint32) << np.uint32(29)) | \
+        rng.integers(0, 4, size=n, dtype=np.uint32)
+    k, _, _ = ts.device_sort(dev(keys))
+    ts.check_device_errors()
+    assert np.array_equal(k.cpu().numpy().view(np.uint32), np.sort(keys))
