@@ -57,14 +57,14 @@ TS_DEV uint64_t mask_of(int kind, int lane) {
 // Theorem 2 (w = m = 64, super-rows of 8 rows): 13 row sorts.
 __constant__ Phase kThm2[13] = {
     // Lemma 1 on every super-row, ascending
-    {1, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},   // round 1
-    {1, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},   // round 2
+    {1, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},   // steps 1-4, first time
+    {1, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},   // steps 1-4, second time
     {0, 0, MOVE_T},                              // final row sort; column sort starts
     {0, 0, MOVE_T},                              // column sort: sort, transpose back
     // Lemma 1 again, odd super-rows descending: their values stay complemented from
     // the first pre-mask (3 = super-row ^ alternation) to the last post-mask (2)
-    {3, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},   // round 1
-    {1, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},   // round 2
+    {3, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},   // steps 1-4, first time
+    {1, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},   // steps 1-4, second time
     {0, 2, MOVE_T},                              // final row sort; column sort starts
     {0, 0, MOVE_T},                              // column sort: sort, transpose back
     {0, 0, MOVE_T},                              // final row sort; to store order
