@@ -89,8 +89,9 @@ enum {
 enum {
     TS_SCHED_AUTO = 0,    /* the plan chosen by the autotuner's table (default) */
     TS_SCHED_SPLIT = 1,   /* alternating-direction binary splits (partition, permute, sort) */
-    TS_SCHED_THM2 = 2,    /* the paper's Theorem 2 schedule: Lemma 1 on super-rows,
-                             column sorts, row sorts (sort and partition) */
+    TS_SCHED_THM2 = 2,    /* the paper's Theorem 2 schedule: Lemma 1 on super-rows of 8
+                             rows, column sorts, row sorts (sort and partition); a 64 x m
+                             tile, m = 64 in one wavefront, m = 128 / 256 spread over 2 / 4 */
     TS_SCHED_BITONIC = 3, /* register row sorts + conflict-free transposes (sort) */
     TS_SCHED_MERGE = 4,   /* sort of uneven tiles up to 2^28 keys: short tiles packed up to
                              eight per wavefront, long tiles cut into 4096-key pieces sorted
@@ -112,13 +113,16 @@ enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2, TS_OP_DEVICE_SORT
  *                         payload_out[k] = payload_in[source of k].
  *   perm_out            : optional int32 [N]: tile-local source index of slot k.
  *   total_len           : N = tile_offsets[num_tiles], the length of the flat arrays;
- *                         the merge schedule places its runs in the workspace by it,
- *                         and skips (and flags) a tile outside [0, N).
- * Supported tile length: 4096 for THM2 and BITONIC, 16384 for SPLIT and NAIVE,
- * 2^28 for MERGE; a longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the
+ *                         every tile must lie in [0, N).  The merge schedule places its
+ *                         runs in the workspace by it and skips (and flags) a tile
+ *                         outside [0, N); the other schedules keep the permutation of a
+ *                         payload without perm_out at workspace index = item index.
+ * Supported tile length: 4096 for BITONIC, 16384 for THM2, SPLIT and NAIVE, 2^28 for
+ * MERGE; a longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the
  * autotuned plan for max_tile_len up to 4096 / 8192 / 16384 and MERGE beyond.
  * The workspace must hold ts_workspace_bytes(TS_OP_SORT, flags, ...) bytes: the
- * merge schedule needs about 16 bytes per key for its runs and work lists.
+ * merge schedule needs about 16 bytes per key for its runs and work lists, a payload
+ * without perm_out 4 bytes per key for the permutation.
  */
 ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out,
                     const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
@@ -134,9 +138,13 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out,
  * [0, num_classes), 1 <= num_classes <= 64.  Output: items grouped by label in
  * ascending label order, input order kept within a label (stable); labels_out,
  * payload_out and perm_out (optional) follow that order.
- * Schedules: SPLIT (default; tiles up to 16384), NAIVE, and THM2 / BITONIC, which
- * partition by sorting the labels with those 4096-key sort schedules (a payload
- * without perm_out then needs ts_workspace_bytes(TS_OP_PARTITION, flags, ...)).
+ * Schedules: SPLIT (default; tiles up to 16384), NAIVE (up to 16384, one payload
+ * channel), and THM2 (up to 16384) / BITONIC (up to 4096), which partition by sorting
+ * the labels with those sort schedules.  Payload: any number of channels (SPLIT moves
+ * the first with the label through LDS and gathers the others through the source
+ * positions at the store; THM2 / BITONIC gather every channel that way); NAIVE with
+ * channels > 1 returns TS_ERR_UNSUPPORTED.  No workspace beyond the error word
+ * (ts_workspace_bytes(TS_OP_PARTITION, ...) is 256 bytes).
  */
 ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
                          const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
@@ -169,9 +177,11 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels,
 /*
  * ts_device_sort -- stable ascending sort of one array of n uint32 keys (the whole
  * array, not tiles), built on the conflict-free 64-way partition: an LSD radix sort
- * whose every pass partitions each 4096-key tile on a 6-bit digit with the split
- * schedule and stores each digit block at its place in the array (Sec. 1: the
- * partition step of a quicksort with pivots, here with digit buckets).  Six passes.
+ * whose every pass partitions each tile on a 6-bit digit with the split schedule and
+ * stores each digit block at its place in the array (Sec. 1: the partition step of a
+ * quicksort with pivots, here with digit buckets).  Six passes.  Tiles hold 4096 keys
+ * when the keys travel alone and 8192 items when a payload word or the permutation
+ * travels with them.
  *   keys_in / keys_out  : uint32 [n] (device, must not alias); with
  *                         TS_FLAG_F32_ORDERED binary32 bit patterns, -0 < +0.
  *   payload_in / out    : optional uint32 [n] moved with the keys (one word per key).
@@ -195,7 +205,8 @@ ts_status ts_device_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint
  * within a label (Sec. 1: partitioning, and its use as the step of a quicksort with
  * pivots).  One pass of ts_device_sort with the label as the digit: per-tile label
  * counts, their prefix in label-major order, and the conflict-free split partition of
- * every 4096-item tile storing each label block at its place in the array.
+ * every tile (4096 labels alone, 8192 with a payload word or the permutation) storing
+ * each label block at its place in the array.
  *   labels_in / out     : uint32 [n] (device, must not alias); labels in
  *                         [0, num_classes), 1 <= num_classes <= 64.
  *   payload_in / out    : optional uint32 [n] moved with the labels (one word each).

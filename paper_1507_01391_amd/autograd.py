@@ -17,10 +17,24 @@ import torch
 
 from . import ops
 
+# Longest tile the backward scatter (tile_permute) moves.
+PERMUTE_MAX_TILE = 16384
+
+
+def _resolve_max_len(offsets, max_tile_len):
+    """max_tile_len, or the longest tile of `offsets` read once (one device sync) when it
+    is not given; passing it keeps forward and backward free of host synchronisation."""
+    ml = ops.longest_tile(offsets) if max_tile_len is None else int(max_tile_len)
+    if ml > PERMUTE_MAX_TILE:
+        raise ValueError(f"tiles of up to {PERMUTE_MAX_TILE} items are differentiable "
+                         f"(the backward scatter's capacity); got max_tile_len {ml}")
+    return ml
+
 
 class Permute(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, pi, offsets, max_tile_len=None):
+        max_tile_len = _resolve_max_len(offsets, max_tile_len)
         # the inverse is kept as 16-bit tile-local indices (every supported tile
         # length fits), so the backward reads 2 bytes per element for it
         inv = torch.empty(pi.shape, dtype=torch.int16, device=pi.device)
@@ -40,6 +54,7 @@ class SortWithPayload(torch.autograd.Function):
     @staticmethod
     def forward(ctx, keys, payload, offsets, max_tile_len=None):
         assert keys.dtype == torch.float32, "keys must be float32"
+        max_tile_len = _resolve_max_len(offsets, max_tile_len)
         k, p, perm = ops.tile_sort(keys.contiguous(), payload.contiguous(), offsets,
                                    max_tile_len=max_tile_len, f32_ordered=True, want_perm=True)
         ctx.save_for_backward(perm, offsets)

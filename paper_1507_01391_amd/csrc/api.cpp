@@ -132,9 +132,6 @@ const char* ts_version(void) { return "tilesort 0.1 (gfx950)"; }
 
 size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t total_len,
                           int64_t max_tile_len, uint32_t channels) {
-    if (op == TS_OP_PARTITION && num_tiles > 0 && channels > 0 &&
-        (sched_of(flags) == TS_SCHED_THM2 || sched_of(flags) == TS_SCHED_BITONIC))
-        return kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
     if (op == TS_OP_DEVICE_SORT)
         return total_len > 0 ? ts::device_sort_layout(total_len, ts::radix_tile(channels > 0), channels > 0).total
                              : kWorkspaceBytes;
@@ -174,16 +171,17 @@ ts_status ts_check(void* workspace, void* stream) {
     return fail(TS_ERR_INVALID, "device reported: %s", msg.c_str());
 }
 
-// Partition as the sorting of labels (the abstract's definition) with a 4096-key
-// sort schedule: Theorem 2 (THM2) or the bitonic network.  The composites carry the
-// position, so the order inside a class is the input order, as for the split
-// schedule.  The payload follows through the permutation like tile_sort's.
+// Partition as the sorting of labels (the abstract's definition) with a sort schedule:
+// Theorem 2 (THM2, tiles up to 16384) or the bitonic network (BITONIC, up to 4096).
+// The composites carry the position, so the order inside a class is the input order,
+// as for the split schedule.  Every payload channel is gathered in the sort kernel's
+// store through the source positions, so no permutation is kept between launches and
+// the call needs no workspace beyond the error word.
 ts_status partition_by_sort(const uint32_t* labels_in, uint32_t* labels_out,
                             const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
                             int64_t elem_stride, int64_t chan_stride, uint32_t num_classes,
                             int32_t* perm_out, const int64_t* tile_offsets, int64_t num_tiles,
-                            int64_t max_tile_len, uint32_t flags, void* workspace,
-                            size_t workspace_bytes, void* stream) {
+                            int64_t max_tile_len, uint32_t flags, void* workspace, void* stream) {
     const int sched = sched_of(flags);
     if (max_tile_len > ts::sort_capacity(sched))
         return fail(TS_ERR_UNSUPPORTED, "tile_partition: max_tile_len %lld > %lld for this schedule",
@@ -204,26 +202,9 @@ ts_status partition_by_sort(const uint32_t* labels_in, uint32_t* labels_out,
     a.offsets = tile_offsets;
     a.num_tiles = num_tiles;
     a.err = (uint32_t*)workspace;
-    if (channels > 0 && a.perm_out == nullptr) {
-        const size_t need = kWorkspaceBytes + (size_t)num_tiles * (size_t)max_tile_len * 4u;
-        if (workspace_bytes < need)
-            return fail(TS_ERR_WORKSPACE, "tile_partition: payload without perm_out needs %zu workspace bytes", need);
-        a.perm_out = (int32_t*)((char*)workspace + kWorkspaceBytes);
-    }
+    a.fuse_pay = channels > 0 ? 1u : 0u;
     e = ts::launch_sort(a, max_tile_len, sched, s);
-    if (e != hipSuccess) return hip_status(e, "tile_partition launch");
-    if (channels > 0) {
-        ts::PermuteArgs p{};
-        p.pay = a.pay;
-        p.pi = a.perm_out;
-        p.direction = TS_GATHER;
-        p.offsets = tile_offsets;
-        p.num_tiles = num_tiles;
-        p.err = a.err;
-        e = ts::launch_permute_split(p, 4096, s);
-        if (e != hipSuccess) return hip_status(e, "tile_partition payload gather launch");
-    }
-    return TS_OK;
+    return hip_status(e, "tile_partition launch");
 }
 
 ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
@@ -241,13 +222,14 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
         return fail(TS_ERR_INVALID, "labels_in and labels_out alias");
     st = check_payload(payload_in, payload_out, channels, elem_stride, chan_stride, true);
     if (st != TS_OK) return st;
-    if (channels > 1)
-        return fail(TS_ERR_UNSUPPORTED, "tile_partition: channels > 1 not supported (got %u)", channels);
     const int sched = sched_of(flags);
     if (sched == TS_SCHED_THM2 || sched == TS_SCHED_BITONIC)
         return partition_by_sort(labels_in, labels_out, payload_in, payload_out, channels, elem_stride,
                                  chan_stride, num_classes, perm_out, tile_offsets, num_tiles,
-                                 max_tile_len, flags, workspace, workspace_bytes, stream);
+                                 max_tile_len, flags, workspace, stream);
+    if (sched == TS_SCHED_NAIVE && channels > 1)
+        return fail(TS_ERR_UNSUPPORTED, "tile_partition: the naive schedule moves one payload channel (got %u)",
+                    channels);
     if (max_tile_len > ts::partition_split_capacity())
         return fail(TS_ERR_UNSUPPORTED, "tile_partition: max_tile_len %lld > %lld",
                     (long long)max_tile_len, (long long)ts::partition_split_capacity());
@@ -444,7 +426,7 @@ ts_status ts_tune(const char* knob, int value) {
     for (int i = 0; i < 3; ++i) {
         if (std::strcmp(knob, plans[i]) != 0) continue;
         const bool ok = value == TS_SCHED_SPLIT || value == TS_SCHED_MERGE || value == TS_SCHED_NAIVE ||
-                        (i == 0 && (value == TS_SCHED_THM2 || value == TS_SCHED_BITONIC));
+                        value == TS_SCHED_THM2 || (i == 0 && value == TS_SCHED_BITONIC);
         if (!ok) return fail(TS_ERR_INVALID, "ts_tune: %s: schedule %d cannot sort such tiles", knob, value);
         g_sort_plan[i] = value;
         return TS_OK;

@@ -8,8 +8,10 @@
 //   1. counts every tile's digits (tile t, digit d -> hist[d][t]),
 //   2. takes the exclusive prefix of hist in digit-major order (goff[d][t]: where tile
 //      t's block of digit d starts in the output array),
-//   3. partitions every 4096-item tile on the digit with its conflict-free binary
-//      splits (partition.hip, MODE 2) and stores each digit block at goff.
+//   3. partitions every tile on the digit with its conflict-free binary splits
+//      (partition.hip, MODE 2) and stores each digit block at goff.
+// Tiles hold 4096 keys when the keys travel alone and 8192 items when a payload word
+// or the permutation travels with them (radix_tile).
 // Each tile partition is stable and the blocks of one digit are laid out in tile order,
 // so every pass is a stable partition of the whole array and six passes sort it.
 #include <algorithm>

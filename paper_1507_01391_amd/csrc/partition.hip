@@ -60,8 +60,9 @@ struct SplitArgs {
     const uint32_t* hist;       // [RADIX_DIGITS][num_tiles] digit counts of every tile
     const uint32_t* goff;       // [RADIX_DIGITS][num_tiles] exclusive prefix of hist in that order
     int64_t n_total;            // length of the whole array (destinations are below it)
-    // MODE 1 only: payload words gathered from global memory at the store (out[v] =
-    // in[position of rank v]), for small batches where a second launch costs more
+    // Payload words gathered from global memory at the store (out[v] = in[position of
+    // rank v]): MODE 1 for small batches, where a second launch costs more; MODE 0 for the
+    // channels after the first
     PayloadRef gpay;
 };
 
@@ -341,8 +342,9 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
 #pragma unroll
                 for (int j = 0; j < CPW; ++j) buffer_store<NTS>(r, off + 256u * j, v[j]);
             }
-            if (MODE == 1 && a.gpay.out != nullptr) {
+            if (MODE != 2 && a.gpay.out != nullptr) {
                 // rank v takes the words of its source position; both stay inside the tile
+                // (MODE 0: the payload channels after the first, which rides in the item)
                 const int64_t es = a.gpay.es, cs = a.gpay.cs;
                 for (uint32_t c = 0; c < a.gpay.channels; ++c) {
                     const uint32_t* src = a.gpay.in + o * es + (int64_t)c * cs;
@@ -352,7 +354,8 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
 #pragma unroll
                     for (int j = 0; j < CPW; ++j) {
                         const int r = 64 * (w * CPW + j) + ls;
-                        v[j] = (r < n) ? src[(int64_t)lo32(e[j]) * es] : 0u;
+                        const uint32_t from = (MODE == 0) ? (hi32(e[j]) >> 16) : lo32(e[j]);
+                        v[j] = (r < n) ? src[(int64_t)from * es] : 0u;
                     }
 #pragma unroll
                     for (int j = 0; j < CPW; ++j) {
@@ -415,6 +418,8 @@ hipError_t launch_partition_split(const PartitionArgs& p, int64_t max_len, hipSt
     a.nbits = p.nbits;
     a.validate = p.validate;
     a.err = p.err;
+    if (p.pay.channels > 1)
+        a.gpay = PayloadRef{p.pay.in + p.pay.cs, p.pay.out + p.pay.cs, p.pay.channels - 1, p.pay.es, p.pay.cs};
     const int64_t* o = p.offsets;
     if (max_len <= 1024) return launch_split_shaped<4, 1024>(a, o, s);
     if (max_len <= 2048) return launch_split_shaped<4, 2048>(a, o, s);

@@ -89,12 +89,20 @@ def _offsets(offsets, n: int, device) -> torch.Tensor:
     return torch.as_tensor(list(offsets), dtype=torch.int64, device=device)
 
 
+def longest_tile(offsets) -> int:
+    """Longest tile of an offsets tensor (int64, T + 1 entries).  Reads one value back
+    from the device, i.e. synchronises; pass max_tile_len to the ops to avoid it."""
+    if not isinstance(offsets, torch.Tensor):
+        offsets = torch.as_tensor(list(offsets), dtype=torch.int64)
+    if offsets.numel() < 2:
+        return 0
+    return int((offsets[1:] - offsets[:-1]).max().item())
+
+
 def _max_len(off: torch.Tensor, max_tile_len: Optional[int]) -> int:
     if max_tile_len is not None:
         return int(max_tile_len)
-    if off.numel() < 2:
-        return 0
-    return int((off[1:] - off[:-1]).max().item())
+    return longest_tile(off)
 
 
 def tile_partition(labels: torch.Tensor, payload: Optional[torch.Tensor] = None, offsets=None,

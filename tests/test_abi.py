@@ -71,6 +71,19 @@ def test_partition_argument_validation(lib):
     # tile too long for any kernel
     rc = lib.tile_partition(fake, P(0x3000), None, None, 0, 1, 0, 64, None, fake, 1, 1 << 20, 0, ws, 256, None)
     assert rc == 2
+    # Theorem 2 partitions tiles of up to 16384 labels, the bitonic network 4096
+    thm2, bitonic, naive = 2 << 8, 3 << 8, 15 << 8
+    rc = lib.tile_partition(fake, P(0x3000), None, None, 0, 1, 0, 64, None, fake, 1, 16385, thm2, ws, 256, None)
+    assert rc == 2
+    rc = lib.tile_partition(fake, P(0x3000), None, None, 0, 1, 0, 64, None, fake, 1, 8192, bitonic, ws, 256, None)
+    assert rc == 2
+    # the naive baseline moves one payload channel; the other schedules any number
+    rc = lib.tile_partition(fake, P(0x3000), fake, P(0x4000), 2, 1, 4096, 64, None, fake, 1, 4096, naive, ws,
+                            256, None)
+    assert rc == 2 and "channel" in _err(lib)
+    # partition needs no workspace beyond the error word, whatever the schedule and payload
+    for sched in (0, 1 << 8, thm2, bitonic):
+        assert lib.ts_workspace_bytes(1, sched, 1000, 1000 * 16384, 16384, 3) == 256
 
 
 def test_sort_argument_validation(lib):
@@ -84,8 +97,10 @@ def test_sort_argument_validation(lib):
     # aliasing
     rc = lib.tile_sort(fake, fake, None, None, 0, 1, 0, None, fake, 1, 4096, 4096, 0, ws, 256, None)
     assert rc == 1 and "alias" in _err(lib)
-    # the bitonic schedule holds 4096 keys per tile
+    # the bitonic schedule holds 4096 keys per tile, Theorem 2 16384
     rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 8192, 8192, 3 << 8, ws, 256, None)
+    assert rc == 2
+    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 16385, 16385, 2 << 8, ws, 256, None)
     assert rc == 2
     # the merge schedule holds 2^28 keys per tile
     rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 1 << 29, (1 << 28) + 1, merge,
@@ -101,6 +116,8 @@ def test_sort_argument_validation(lib):
 
 def test_tune_knob_validation(lib):
     assert lib.ts_tune(b"sort_plan_8192", 3) == 1          # bitonic cannot hold 8192 keys
+    assert lib.ts_tune(b"sort_plan_16384", 2) == 0         # Theorem 2 can
+    assert lib.ts_tune(b"sort_plan_16384", 4) == 0
     assert lib.ts_tune(b"sort_plan_4096", 7) == 1
     assert lib.ts_tune(b"merge_pack", 2) == 1
     assert lib.ts_tune(b"no_such_knob", 0) == 1

@@ -95,3 +95,20 @@ def test_sort_with_payload_gradcheck_fp64(ts):
     pay = torch.randn(150, dtype=torch.float64, device="cuda", requires_grad=True)
     f = lambda p: ts.sort_with_payload(keys, p, off)[1]
     assert torch.autograd.gradcheck(f, (pay,), eps=1e-6, atol=1e-9)
+
+
+def test_sort_with_payload_rejects_rows_beyond_backward_capacity(ts):
+    """The backward scatter moves tiles of up to 16384 items: a longer row is refused in
+    the forward, before any work, instead of failing in the backward."""
+    keys = torch.zeros(16385, dtype=torch.float32, device="cuda", requires_grad=True)
+    pay = torch.zeros(16385, dtype=torch.float32, device="cuda", requires_grad=True)
+    off = torch.tensor([0, 16385], dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError, match="16384"):
+        ts.sort_with_payload(keys, pay, off)
+    with pytest.raises(ValueError, match="16384"):
+        ts.sort_with_payload(keys, pay, off, 16385)
+    # exactly at the capacity both directions run
+    off = torch.tensor([0, 16384], dtype=torch.int64, device="cuda")
+    sk, sp, _ = ts.sort_with_payload(keys[:16384], pay[:16384], off, 16384)
+    (sk.sum() + sp.sum()).backward()
+    assert bool((keys.grad[:16384] == 1).all()) and bool((pay.grad[:16384] == 1).all())

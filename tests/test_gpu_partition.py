@@ -27,7 +27,8 @@ def run_and_compare(ts, oracle, labels, payload, off, num_classes, schedule, max
     assert np.array_equal(host_u32(lab_out), want_l)
     assert np.array_equal(host_i32(perm), want_perm)
     if payload is not None:
-        assert np.array_equal(host_u32(pay_out), want_p)
+        want_p = np.asarray(want_p).view(np.uint32)
+        assert np.array_equal(host_u32(pay_out).reshape(want_p.shape), want_p)
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
@@ -149,3 +150,55 @@ def test_strided_payload_through_c_abi(ts, oracle):
     assert np.array_equal(lab_out.cpu().numpy().view(np.uint32), wl)
     assert np.array_equal(got[:, 0], wp)
     assert not got[:, 1:].any()          # the other words of each struct are untouched
+
+
+@pytest.mark.parametrize("cap", [8192, 16384])
+def test_thm2_wide_partition(ts, oracle, cap):
+    """Partition as the sorting of labels with Theorem 2 on 64 x 128 and 64 x 256 tiles."""
+    rng = np.random.default_rng(cap + 9)
+    sizes = np.array([cap, cap - 1, 4097, 4096, 1, 0, cap // 2 + 3, cap])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    labels = rng.integers(0, 64, size=off[-1], dtype=np.uint32)
+    labels[: cap] = np.repeat(np.arange(64, dtype=np.uint32), cap // 64)   # exactly m copies
+    labels[: cap] = rng.permutation(labels[: cap])
+    payload = rng.standard_normal(off[-1]).astype(np.float32)
+    run_and_compare(ts, oracle, labels, payload, off, 64, "thm2", max_len=cap)
+
+
+@pytest.mark.parametrize("schedule", ["thm2", "bitonic", "split"])
+def test_payload_tiles_not_starting_at_zero(ts, oracle, schedule):
+    """Tiles that start past item 0 of the arrays (a sub-range of a larger batch), with a
+    payload and no perm_out: the payload follows the labels and nothing outside the
+    tiles' ranges is written."""
+    import torch
+    from tests.gpu_util import dev, host_u32
+    rng = np.random.default_rng(55)
+    n = 4096 * 6
+    labels = rng.integers(0, 64, size=n, dtype=np.uint32)
+    payload = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    off = np.array([4096, 8192, 12000, 16000], np.int64)
+    lo = torch.zeros(n, dtype=torch.int32, device="cuda")
+    po = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ts.tile_partition(dev(labels), dev(payload), dev(off), 64, max_tile_len=4096, schedule=schedule,
+                      want_perm=False, labels_out=lo, payload_out=po)
+    ts.check_device_errors()
+    wl, wp, _ = oracle.tile_partition(labels[4096:16000], payload[4096:16000], off - 4096, num_classes=64)
+    gl, gp = host_u32(lo), host_u32(po)
+    assert np.array_equal(gl[4096:16000], wl) and np.array_equal(gp[4096:16000], wp)
+    assert not gl[:4096].any() and not gl[16000:].any()
+    assert not gp[:4096].any() and not gp[16000:].any()
+
+
+@pytest.mark.parametrize("schedule", ["split", "thm2", "bitonic"])
+@pytest.mark.parametrize("cap", [4096, 16384])
+def test_multichannel_payload(ts, oracle, schedule, cap):
+    """Three channel-planar payload words per item: the first rides with the label, the
+    others follow it through the source positions."""
+    if schedule == "bitonic" and cap > 4096:
+        pytest.skip("the bitonic schedule sorts tiles of up to 4096 keys")
+    rng = np.random.default_rng(cap + 17)
+    sizes = np.array([cap, cap - 1, 37, 0, cap // 2, cap])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    labels = rng.integers(0, 64, size=off[-1], dtype=np.uint32)
+    payload = rng.integers(0, 2**32, size=(3, off[-1]), dtype=np.uint32)
+    run_and_compare(ts, oracle, labels, payload, off, 64, schedule, max_len=cap)

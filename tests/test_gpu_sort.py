@@ -78,7 +78,7 @@ def test_f32_keys_with_special_values(ts, oracle, schedule):
     run_and_compare(ts, oracle, x.view(np.uint32), payload.view(np.uint32), off, schedule, f32=True)
 
 
-@pytest.mark.parametrize("schedule", ["split", "naive", "auto", "merge"])
+@pytest.mark.parametrize("schedule", ["split", "naive", "auto", "merge", "thm2"])
 @pytest.mark.parametrize("cap", [8192, 16384])
 def test_large_tiles(ts, oracle, schedule, cap):
     rng = np.random.default_rng(cap)
@@ -241,3 +241,53 @@ def test_split_payload_fused_and_routed(ts, oracle, num_tiles):
     assert np.array_equal(k.cpu().numpy().view(np.uint32), wk)
     assert np.array_equal(perm.cpu().numpy(), wperm)
     assert np.array_equal(p.cpu().numpy().view(np.uint32), wp)
+
+
+# ---- Theorem 2 on 64 x 128 and 64 x 256 tiles (two and four wavefronts per tile) -----
+
+@pytest.mark.parametrize("cap", [8192, 16384])
+def test_thm2_wide_distributions(ts, oracle, cap):
+    """Every key distribution of the segmented workload, ragged lengths around both
+    capacities, two planar payload channels."""
+    rng = np.random.default_rng(cap + 3)
+    tiles = []
+    for kind in ("uniform", "zipf", "presorted", "reversed", "equal", "binary"):
+        for n in (cap, cap - 1, int(rng.integers(4097, cap)), int(rng.integers(1, 4097))):
+            if kind == "uniform":
+                k = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+            elif kind == "zipf":
+                k = np.minimum(rng.zipf(1.2, size=n), 2**32 - 1).astype(np.uint32)
+            elif kind == "presorted":
+                k = np.sort(rng.integers(0, 2**32, size=n, dtype=np.uint32))
+            elif kind == "reversed":
+                k = np.sort(rng.integers(0, 2**32, size=n, dtype=np.uint32))[::-1].copy()
+            elif kind == "equal":
+                k = np.full(n, 0xFFFFFFFF if rng.random() < 0.5 else 12345, np.uint32)
+            else:
+                k = (rng.random(n) < 0.5).astype(np.uint32)
+            tiles.append(k)
+    off = np.concatenate([[0], np.cumsum([len(t) for t in tiles])]).astype(np.int64)
+    keys = np.concatenate(tiles)
+    payload = np.stack([np.arange(off[-1], dtype=np.uint32),
+                        rng.integers(0, 2**32, size=off[-1], dtype=np.uint32)])
+    run_and_compare(ts, oracle, keys, payload, off, "thm2", max_len=cap)
+
+
+@pytest.mark.parametrize("cap", [8192, 16384])
+def test_thm2_wide_f32_and_edges(ts, oracle, cap):
+    rng = np.random.default_rng(cap + 4)
+    sizes = [0, 1, 2, 63, 64, 65, 4095, 4096, 4097, cap // 2, cap - 64, cap - 1, cap]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = rng.standard_normal(int(off[-1])).astype(np.float32)
+    x[:8] = np.array([-np.inf, np.inf, -0.0, 0.0, 1e-40, -1e-40, 3.0, -3.0], np.float32)
+    rng.shuffle(x)
+    run_and_compare(ts, oracle, x.view(np.uint32), None, off, "thm2", max_len=cap, f32=True)
+
+
+def test_thm2_tile_longer_than_capacity_is_reported(ts):
+    from tests.gpu_util import dev
+    keys = np.zeros(16385, np.uint32)
+    ts.tile_sort(dev(keys), None, dev(np.array([0, 16385], np.int64)), max_tile_len=16384,
+                 schedule="thm2")
+    with pytest.raises(RuntimeError, match="capacity"):
+        ts.check_device_errors()

@@ -1,0 +1,242 @@
+"""CPU model of the Theorem 2 kernel for 64 x m tiles spread over H = m / 64 wavefronts
+(m = 128, 256): the LDS word maps of its moves and exchanges are checked for bounds,
+bijectivity and bank conflicts under the measured gfx950 model, and the whole data flow
+(register row sorts, exchanges between wavefronts, super-row moves, column sorts, the
+final move to store order) is replayed on small-integer inputs with ties and padding and
+compared with a stable argsort.
+
+Wavefront h holds columns 64h .. 64h+63 of every row: lane L = row L, register c = column
+64h + c.  Theorem 2 (Sec. 2) with super-rows of 8 rows; Lemma 1's condition 8 <= sqrt(m)
+holds for every m >= 64.
+"""
+import numpy as np
+import pytest
+
+MOVE_WORDS = 64 * 65
+LANES = np.arange(64)
+
+
+def wide_words(H):
+    return max(64 * (64 * H + 1), H * MOVE_WORDS, H * 16 * 64 * 2)
+
+
+def move_dst(move, M, L, c):
+    """(row, column) destination of (row L, column c) for the super-row moves."""
+    i = L & 7
+    if move == "RM2CM":
+        p = i * M + c
+        return (L & ~7) + (p & 7), p >> 3
+    p = 8 * c + i
+    return (L & ~7) + p // M, p % M
+
+
+def skew(move, M, cd):
+    return cd // (M // 8) if move == "RM2CM" else cd & 7
+
+
+def write_word(move, M, h, L, c):
+    if move == "FINAL":
+        return L * (M + 1) + 64 * h + c
+    Ld, cd = move_dst(move, M, L, 64 * h + c)
+    return cd * 64 + ((Ld + skew(move, M, cd)) & 63)
+
+
+def read_word(move, M, h, L, c):
+    k = 64 * h + c
+    if move == "FINAL":
+        return 64 * k + L + (64 * k) // M
+    return k * 64 + ((L + skew(move, M, k)) & 63)
+
+
+def conflicts_b32(words):
+    """Excess cycles of one 32-bit wave instruction: two 32-lane halves over 32 banks,
+    distinct words on one bank conflict (the measured gfx950 model)."""
+    extra = 0
+    for half in (words[:32], words[32:]):
+        banks = {}
+        for wd in half:
+            banks.setdefault(wd % 32, set()).add(wd)
+        extra += max(len(s) for s in banks.values()) - 1
+    return extra
+
+
+@pytest.mark.parametrize("H", [2, 4])
+@pytest.mark.parametrize("move", ["RM2CM", "CM2RM", "FINAL"])
+def test_wide_moves_bijective_in_bounds_conflict_free(H, move):
+    M = 64 * H
+    written = {}
+    for h in range(H):
+        for c in range(64):
+            ws = [write_word(move, M, h, L, c) for L in range(64)]
+            rs = [read_word(move, M, h, L, c) for L in range(64)]
+            assert conflicts_b32(ws) == 0, (h, c)
+            assert conflicts_b32(rs) == 0, (h, c)
+            assert max(ws + rs) < wide_words(H) and min(ws + rs) >= 0
+            for L, wd in enumerate(ws):
+                assert wd not in written
+                written[wd] = (h, L, c)
+    # every read meets exactly the item that the move sends there
+    for h in range(H):
+        for L in range(64):
+            for c in range(64):
+                hs, Ls, cs = written[read_word(move, M, h, L, c)]
+                if move == "FINAL":
+                    # rank Ls*M + 64 hs + cs lands in register c of lane L, wavefront h,
+                    # as rank 64 (64 h + c) + L
+                    assert Ls * M + 64 * hs + cs == 64 * (64 * h + c) + L
+                else:
+                    assert move_dst(move, M, Ls, 64 * hs + cs) == (L, 64 * h + c)
+
+
+@pytest.mark.parametrize("H", [2, 4])
+def test_wide_exchange_slots(H):
+    """Exchange of 16 registers between wavefronts as 64-bit words: slot (16 h + j) 64 + L;
+    64-bit writes are served 16 lanes at a time, reads 32 lanes at a time, over 64 banks."""
+    top = 0
+    for h in range(H):
+        for j in range(16):
+            slots = [(16 * h + j) * 64 + L for L in range(64)]
+            top = max(top, 2 * max(slots) + 1)
+            for ph in range(0, 64, 16):    # writes: 16 slots = 32 consecutive words
+                wd = {(2 * s) % 64 for s in slots[ph:ph + 16]}
+                assert len(wd) == 16
+            for ph in (0, 32):             # reads: 32 slots distinct modulo 32
+                assert len({s % 32 for s in slots[ph:ph + 32]}) == 32
+    assert top < wide_words(H)
+
+
+# ---- data flow of the whole kernel ---------------------------------------------------
+
+FULL = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def mask_of(kind):
+    if kind == 0:
+        on = np.zeros(64, bool)
+    elif kind == 1:
+        on = (LANES & 1) == 1
+    elif kind == 2:
+        on = ((LANES >> 3) & 1) == 1
+    else:
+        on = ((LANES & 1) ^ ((LANES >> 3) & 1)) == 1
+    return np.where(on, FULL, np.uint64(0))
+
+
+def bitonic_merge_regs(v):
+    """In-register ascending bitonic merge over the last axis (stages 32 .. 1)."""
+    j = 32
+    while j >= 1:
+        idx = np.arange(64)
+        lo = idx[(idx & j) == 0]
+        hi = lo ^ j
+        a, b = v[..., lo].copy(), v[..., hi].copy()
+        v[..., lo] = np.minimum(a, b)
+        v[..., hi] = np.maximum(a, b)
+        j //= 2
+    return v
+
+
+def row_sort_regs(v):
+    return np.sort(v, axis=-1)
+
+
+def wide_row_sort(V, H):
+    """V[h, L, c]: the steps of the kernel's row sort across H wavefronts."""
+    for h in range(H):
+        m1 = FULL if h & 1 else np.uint64(0)
+        V[h] = row_sort_regs(V[h] ^ m1) ^ m1
+
+    def cross(partner_bit, asc_of):
+        W = V.copy()
+        for h in range(H):
+            hp = h ^ partner_bit
+            keep_min = (h < hp) == asc_of(h)
+            W[h] = np.minimum(V[h], V[hp]) if keep_min else np.maximum(V[h], V[hp])
+        V[:] = W
+
+    asc128 = (lambda h: True) if H == 2 else (lambda h: ((h >> 1) & 1) == 0)
+    cross(1, asc128)
+    for h in range(H):
+        m2 = np.uint64(0) if asc128(h) else FULL
+        V[h] = bitonic_merge_regs(V[h] ^ m2) ^ m2
+    if H == 4:
+        cross(2, lambda h: True)
+        cross(1, lambda h: True)
+        for h in range(H):
+            V[h] = bitonic_merge_regs(V[h])
+    return V
+
+
+def cross_move(V, H, move):
+    M = 64 * H
+    lds = np.zeros(wide_words(H), dtype=np.uint64)
+    for h in range(H):
+        for c in range(64):
+            for L in range(64):
+                lds[write_word(move, M, h, L, c)] = V[h, L, c]
+    W = np.empty_like(V)
+    for h in range(H):
+        for c in range(64):
+            for L in range(64):
+                W[h, L, c] = lds[read_word(move, M, h, L, c)]
+    return W
+
+
+def transpose_in_wave(V):
+    # pitch-65 transpose inside each wavefront: (L, c) -> (c, L)
+    return np.ascontiguousarray(np.swapaxes(V, 1, 2))
+
+
+PHASES = [  # (pre mask, post mask, sort, move), the kernel's phase table
+    (1, 1, "row", "RM2CM"), (0, 0, "row", "CM2RM"),
+    (1, 1, "row", "RM2CM"), (0, 0, "row", "CM2RM"),
+    (0, 0, "row", "T"), (0, 0, "col", "T"),
+    (3, 1, "row", "RM2CM"), (0, 0, "row", "CM2RM"),
+    (1, 1, "row", "RM2CM"), (0, 0, "row", "CM2RM"),
+    (0, 2, "row", "T"), (0, 0, "col", "T"),
+    (0, 0, "row", "FINAL"),
+]
+
+
+def run_wide_kernel(keys, H):
+    n = len(keys)
+    M = 64 * H
+    assert n <= 64 * M
+    V = np.empty((H, 64, 64), dtype=np.uint64)
+    for h in range(H):
+        for c in range(64):
+            i = 64 * (64 * h + c) + LANES
+            k = np.where(i < n, keys[np.minimum(i, max(n - 1, 0))] if n else 0, 0xFFFFFFFF)
+            V[h, :, c] = (k.astype(np.uint64) << np.uint64(32)) | i.astype(np.uint64)
+    for pre, post, sort, move in PHASES:
+        V = V ^ mask_of(pre)[None, :, None]
+        V = wide_row_sort(V, H) if sort == "row" else row_sort_regs(V)
+        V = V ^ mask_of(post)[None, :, None]
+        V = transpose_in_wave(V) if move == "T" else cross_move(V, H, move)
+    out = np.empty(64 * M, dtype=np.uint64)
+    for h in range(H):
+        for c in range(64):
+            out[64 * (64 * h + c) + LANES] = V[h, :, c]
+    return out[:n]
+
+
+@pytest.mark.parametrize("H,n,seed,hi", [(2, 8192, 1, 2**32), (2, 5000, 2, 7), (4, 16384, 3, 3),
+                                         (4, 9999, 4, 2**32), (2, 1, 5, 9), (4, 64, 6, 1)])
+def test_wide_kernel_data_flow_sorts(H, n, seed, hi):
+    rng = np.random.default_rng(seed)
+    keys = rng.integers(0, hi, size=n, dtype=np.uint64).astype(np.uint32)
+    out = run_wide_kernel(keys, H)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal((out >> np.uint64(32)).astype(np.uint32), keys[order])
+    assert np.array_equal((out & np.uint64(0xFFFFFFFF)).astype(np.int64), order)
+
+
+def test_wide_kernel_data_flow_01_inputs():
+    """0-1 inputs (the 0-1 principle of Lemma 1's proof) at both widths."""
+    rng = np.random.default_rng(11)
+    for H in (2, 4):
+        for _ in range(3):
+            keys = (rng.random(64 * 64 * H) < rng.random()).astype(np.uint32)
+            out = run_wide_kernel(keys, H)
+            assert np.array_equal((out & np.uint64(0xFFFFFFFF)).astype(np.int64),
+                                  np.argsort(keys, kind="stable"))
