@@ -92,10 +92,13 @@ enum {
     TS_SCHED_THM2 = 2,    /* the paper's Theorem 2 schedule: Lemma 1 on super-rows of 8
                              rows, column sorts, row sorts (sort and partition); a 64 x m
                              tile, m = 64 in one wavefront, m = 128 / 256 spread over 2 / 4 */
-    TS_SCHED_BITONIC = 3, /* register row sorts + conflict-free transposes (sort) */
+    TS_SCHED_BITONIC = 3, /* Batcher's network: register stages + conflict-free transposes,
+                             tiles of 8192 / 16384 over 2 / 4 wavefronts (sort, partition) */
     TS_SCHED_MERGE = 4,   /* sort of uneven tiles up to 2^28 keys: short tiles packed up to
-                             eight per wavefront, long tiles cut into 4096-key pieces sorted
-                             like BITONIC, then rounds of pairwise bitonic merges (sort) */
+                             eight per wavefront, tiles up to 32768 keys sorted whole by one
+                             workgroup of up to 8 wavefronts, longer tiles cut into 4096-key
+                             pieces sorted like BITONIC, then rounds of pairwise bitonic
+                             merges (sort) */
     TS_SCHED_NAIVE = 15   /* baseline: plain LDS counting / direct scatter, with bank
                              conflicts (all three ops) */
 };
@@ -117,8 +120,7 @@ enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2, TS_OP_DEVICE_SORT
  *                         runs in the workspace by it and skips (and flags) a tile
  *                         outside [0, N); the other schedules keep the permutation of a
  *                         payload without perm_out at workspace index = item index.
- * Supported tile length: 4096 for BITONIC, 16384 for THM2, SPLIT and NAIVE, 2^28 for
- * MERGE; a longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the
+ * Supported tile length: 16384 for BITONIC, THM2, SPLIT and NAIVE, 2^28 for MERGE; a longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the
  * autotuned plan for max_tile_len up to 4096 / 8192 / 16384 and MERGE beyond.
  * The workspace must hold ts_workspace_bytes(TS_OP_SORT, flags, ...) bytes: the
  * merge schedule needs about 16 bytes per key for its runs and work lists, a payload
@@ -139,8 +141,8 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out,
  * ascending label order, input order kept within a label (stable); labels_out,
  * payload_out and perm_out (optional) follow that order.
  * Schedules: SPLIT (default; tiles up to 16384), NAIVE (up to 16384, one payload
- * channel), and THM2 (up to 16384) / BITONIC (up to 4096), which partition by sorting
- * the labels with those sort schedules.  Payload: any number of channels (SPLIT moves
+ * channel), and THM2 / BITONIC (up to 16384), which partition by sorting the labels
+ * with those sort schedules.  Payload: any number of channels (SPLIT moves
  * the first with the label through LDS and gathers the others through the source
  * positions at the store; THM2 / BITONIC gather every channel that way); NAIVE with
  * channels > 1 returns TS_ERR_UNSUPPORTED.  No workspace beyond the error word
@@ -289,6 +291,9 @@ ts_status ts_lds_probe(const uint32_t* lane_words, int op, int width, int iters,
    "naive_oneshot" -- the same choice for the naive-LDS kernels (default 0).
    "merge_pack" -- 1: tiles of up to 2048 keys share a wavefront in the merge
       schedule, 0: one tile per wavefront.
+   "merge_wide" -- longest tile the merge schedule sorts whole in one workgroup of
+      2 / 4 / 8 wavefronts: 8192, 16384 or 32768 (default); 4096: none, longer tiles
+      go through 4096-key pieces and merge rounds.
    "sort_plan_4096", "sort_plan_8192", "sort_plan_16384" -- the TS_SCHED_* value that
       tile_sort's AUTO uses for max_tile_len up to that length.
    "sort_small_batch" -- AUTO sorts batches of at most this many tiles of up to 4096

@@ -417,6 +417,12 @@ ts_status ts_tune(const char* knob, int value) {
         g_sort_small_batch = value;
         return TS_OK;
     }
+    if (std::strcmp(knob, "merge_wide") == 0) {
+        if (value != 4096 && value != 8192 && value != 16384 && value != 32768)
+            return fail(TS_ERR_INVALID, "ts_tune: merge_wide must be 4096, 8192, 16384 or 32768");
+        ts::set_merge_wide(value);
+        return TS_OK;
+    }
     if (std::strcmp(knob, "merge_pack") == 0) {
         if (value != 0 && value != 1) return fail(TS_ERR_INVALID, "ts_tune: merge_pack must be 0 or 1");
         ts::set_merge_pack(value);
@@ -426,7 +432,7 @@ ts_status ts_tune(const char* knob, int value) {
     for (int i = 0; i < 3; ++i) {
         if (std::strcmp(knob, plans[i]) != 0) continue;
         const bool ok = value == TS_SCHED_SPLIT || value == TS_SCHED_MERGE || value == TS_SCHED_NAIVE ||
-                        value == TS_SCHED_THM2 || (i == 0 && value == TS_SCHED_BITONIC);
+                        value == TS_SCHED_THM2 || value == TS_SCHED_BITONIC;
         if (!ok) return fail(TS_ERR_INVALID, "ts_tune: %s: schedule %d cannot sort such tiles", knob, value);
         g_sort_plan[i] = value;
         return TS_OK;

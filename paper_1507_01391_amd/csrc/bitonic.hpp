@@ -180,5 +180,65 @@ TS_DEV void bitonic_merge4096(uint32_t* A, uint64_t (&v)[R], int lane) {
     layout_move(A, v, MOVE_T, lane);
 }
 
+// ---------------------------------------------------------------------------------
+// Tiles spread over H wavefronts of one workgroup (H = 2, 4, 8): every wavefront holds
+// 4096 items in its 64 registers x 64 lanes.
+
+// Compare-exchange of every register with the same register of wavefront hp (same
+// lane): the wavefront with the lower index keeps the smaller composite when `asc`.
+// Sixteen registers at a time go through LDS as 64-bit words, lane L of wavefront h at
+// slot (16 h + j) 64 + L of X (16 H x 64 slots): 16 (writes) or 32 (reads) consecutive
+// 8-byte slots per phase, no bank conflicts.  All H wavefronts take part (barriers).
+TS_DEV void cross_wave_stage(uint64_t* X, uint64_t (&v)[R], int h, int hp, bool asc, int lane) {
+    const bool keep_min = (h < hp) == asc;
+#pragma unroll
+    for (int g = 0; g < R; g += 16) {
+        __syncthreads();  // earlier readers of X are done
+#pragma unroll
+        for (int j = 0; j < 16; ++j) X[(16 * h + j) * 64 + lane] = v[g + j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const uint64_t y = X[(16 * hp + j) * 64 + lane];
+            const uint64_t x = v[g + j];
+            v[g + j] = keep_min ? (y < x ? y : x) : (y < x ? x : y);
+        }
+    }
+}
+
+// Words of LDS the wide bitonic sort needs: one transpose array per wavefront (the
+// exchange buffer of cross_wave_stage, 16 H x 64 x 2 words, fits in it).
+template <int H>
+constexpr int wide_bitonic_words() { return H * MOVE_WORDS; }
+
+// Batcher's bitonic sort of 4096 H composites held by H wavefronts (wavefront h = the
+// item indices 4096 h .. 4096 h + 4095).  Every wavefront sorts its own 4096 items
+// (descending in odd wavefronts); each further level compares across wavefronts on the
+// wavefront bits and finishes inside each wavefront with the 12 merge stages of
+// bitonic_merge4096.  On exit register c of lane L in wavefront h holds rank
+// 4096 h + 64 c + L.  A: wide_bitonic_words<H>() words, wavefront h uses its own
+// MOVE_WORDS part for the transposes.
+template <int H>
+TS_DEV void bitonic_sort_wide(uint32_t* A, uint64_t (&v)[R], int h, int lane) {
+    uint64_t* X = (uint64_t*)A;
+    uint32_t* Aw = A + h * MOVE_WORDS;
+    const uint64_t m0 = (h & 1) ? ~0ull : 0ull;
+    xor_all(v, m0);
+    bitonic_sort4096(Aw, v, lane);
+    xor_all(v, m0);
+#pragma unroll
+    for (int k = 1; (1 << k) <= H; ++k) {
+        // level 4096 * 2^k: blocks of 2^k wavefronts, ascending where bit k of h is clear
+        const bool asc = ((h >> k) & 1) == 0;
+#pragma unroll
+        for (int b = k - 1; b >= 0; --b) cross_wave_stage(X, v, h, h ^ (1 << b), asc, lane);
+        __syncthreads();  // the exchange buffer overlaps the transpose arrays
+        const uint64_t m = asc ? 0ull : ~0ull;
+        xor_all(v, m);
+        bitonic_merge4096(Aw, v, lane);
+        xor_all(v, m);
+    }
+}
+
 }  // namespace bt
 }  // namespace ts

@@ -126,12 +126,13 @@ template <int CPW, bool NT = false, typename T>
 TS_DEV void load_columns(const T* __restrict__ base, int64_t stride, int64_t o, int n, int c0,
                          int lane, T (&out)[CPW], const void* fallback) {
     const bool any = n > 0;
+    const uint32_t nn = any ? (uint32_t)n : 0u;  // a negative n loads nothing
     if (stride == 1) {
         const char* tb = any ? (const char*)(base + o) : (const char*)fallback;
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
             const uint32_t i = (uint32_t)(64 * (c0 + j) + lane);
-            const uint32_t off = (i < (uint32_t)n) ? i * (uint32_t)sizeof(T) : 0u;
+            const uint32_t off = (i < nn) ? i * (uint32_t)sizeof(T) : 0u;
             const T* p = (const T*)(tb + off);
             out[j] = NT ? __builtin_nontemporal_load(p) : *p;
         }

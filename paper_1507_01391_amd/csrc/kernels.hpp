@@ -122,7 +122,8 @@ constexpr int MERGE_POS_BITS = 28;         // tile positions fit in 28 bits
 constexpr int64_t MERGE_MAX_TILE = int64_t(1) << MERGE_POS_BITS;
 constexpr int MERGE_MAX_ROUNDS = 16;       // log2(MERGE_MAX_TILE / MERGE_PIECE)
 constexpr int MERGE_COUNTER_WORD = 16;     // first counter word in the workspace header
-constexpr int MERGE_COUNTER_BYTES = 96;    // words 16 .. 39: 4 bins, pieces, rounds 0 .. 15 at 8 + r
+constexpr int MERGE_COUNTER_BYTES = 96;    // words 16 .. 39: bins 0 .. 3, pieces, bins 4 .. 6,
+                                           // rounds 0 .. 15 at 8 + r
 
 // Byte offsets of the regions a merge-schedule sort carves out of the workspace.
 struct MergeLayout {
@@ -135,7 +136,7 @@ MergeLayout merge_layout(int64_t num_tiles, int64_t total_len, int64_t max_len);
 struct MergeArgs {
     SortArgs s;
     uint32_t* counters;      // MERGE_COUNTER_BYTES, zeroed by the launcher
-    uint64_t* bins;          // 4 lists of num_tiles entries (tile << 16)
+    uint64_t* bins;          // 7 lists of num_tiles entries (tile << 16)
     uint64_t* pieces;        // cap entries (tile << 16 | piece)
     uint64_t* round_lists;   // rounds x cap entries (tile << 16 | output piece)
     int32_t* coranks;        // rounds x cap x 2
@@ -144,12 +145,14 @@ struct MergeArgs {
     int64_t cap;
     int rounds;
     int pack;                // nonzero: up to 8 short tiles share one wavefront
+    int64_t wide_max;        // tiles of up to this many keys are sorted whole by one workgroup
     int64_t max_len;
     int64_t total_len;       // keys of all tiles; every tile must lie in [0, total_len)
 };
 hipError_t launch_sort_merge(const SortArgs& s, int64_t total_len, int64_t max_len, void* ws,
                              hipStream_t st);
 void set_merge_pack(int v);
+void set_merge_wide(int v);
 
 // Device properties cached by the API layer.
 int num_cus();

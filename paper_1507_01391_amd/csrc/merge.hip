@@ -2,10 +2,14 @@
 // launches that a stream capture can record once and replay.
 //
 // The tile-local problem is the paper's sorting problem (Sec. 1, "Problems of
-// interest"); its schedules assume a w x m tile resident in one workgroup.  Here a
-// tile longer than one wavefront's 4096 items is cut into pieces, every piece is sorted
-// in registers by the bitonic network of bitonic.hpp (conflict-free transposes through
-// LDS), and sorted runs are merged pairwise, doubling the run length per round.  A
+// interest"); its schedules assume a w x m tile resident in one workgroup.  Tiles of up
+// to 4096 keys are sorted in one wavefront (packed up to eight per wavefront), tiles of
+// 4097 .. 32768 keys whole in one workgroup of 2, 4 or 8 wavefronts (the bitonic network
+// spread over the wavefronts, bitonic_sort_wide: the tile stays resident, so every key
+// is read and written once).  A longer tile is cut into 4096-key pieces, every piece
+// is sorted in registers by the bitonic network of bitonic.hpp (conflict-free
+// transposes through LDS), and sorted runs are merged pairwise, doubling the run length
+// per round.  A
 // merge step is the last level of the same bitonic network, applied to 4096 outputs at
 // a time: a merge-path co-rank search picks the A and B ranges that produce them, A is
 // loaded ascending and B descending (a bitonic sequence) and 12 merge stages sort it.
@@ -17,9 +21,10 @@
 //
 // Sequence of launches (all on one stream, no host synchronisation):
 //   1. clear the work counters (a fill kernel, so the sequence stays capturable);
-//   2. bin: one thread per tile appends the tile to a packing bin or its pieces to the
-//      piece list, and its output pieces to the list of every merge round it needs;
-//   3. sort: one persistent launch per packing bin and one for the pieces;
+//   2. bin: one thread per tile appends the tile to a packing bin or a workgroup bin,
+//      or its pieces to the piece list and its output pieces to the list of every merge
+//      round it needs;
+//   3. sort: one persistent launch per bin and one for the pieces;
 //   4. per merge round: co-rank search (one thread per output piece), then the merge.
 // The last store of every tile writes keys, the permutation and the payload, gathered
 // from the input by the permutation.
@@ -40,6 +45,15 @@ constexpr int SLOT_SHIFT = 60;  // slot (3 bits) above key and position
 constexpr uint64_t PAD = ~uint64_t(0);
 
 int g_merge_pack = 1;
+// Longest tile sorted whole by one workgroup (4096: none, every longer tile goes
+// through pieces and merge rounds); tuning knob "merge_wide".
+int g_merge_wide = 32768;
+
+// Bins: 0 .. 3 pack 8 / 4 / 2 / 1 tiles of up to 512 / 1024 / 2048 / 4096 keys per
+// wavefront; 4 .. 6 hold tiles of up to 8192 / 16384 / 32768 keys, one per workgroup of
+// 2 / 4 / 8 wavefronts.  Counter word of bin b (the piece list counts at word 4).
+constexpr int NUM_BINS = 7;
+TS_DEV int bin_counter(int b) { return b < 4 ? b : b + 1; }
 
 TS_DEV uint64_t make_comp(uint32_t slot, uint32_t key, uint32_t pos) {
     return ((uint64_t)slot << SLOT_SHIFT) | ((uint64_t)key << POS_BITS) | pos;
@@ -99,16 +113,17 @@ __global__ __launch_bounds__(256) void merge_bin_kernel(MergeArgs a) {
         if (too_long || bad) n = 0;
         int bin = -1;
         if (n > 0 && n <= K) bin = a.pack ? (n <= 512 ? 0 : n <= 1024 ? 1 : n <= 2048 ? 2 : 3) : 3;
-        for (int b = 0; b < 4; ++b) {
+        else if (n > K && n <= a.wide_max) bin = n <= 2 * K ? 4 : n <= 4 * K ? 5 : 6;
+        for (int b = 0; b < NUM_BINS; ++b) {
             const uint64_t m = ballot(bin == b);
             if (m == 0) continue;
             const int leader = __builtin_ctzll(m);
             uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&a.counters[b], (uint32_t)popc64(m));
+            if (lane == leader) base = atomicAdd(&a.counters[bin_counter(b)], (uint32_t)popc64(m));
             base = (uint32_t)__shfl((int)base, leader);
             if (bin == b) a.bins[b * T + base + count_below(m)] = entry(t, 0);
         }
-        const uint32_t np = (n > K) ? (uint32_t)((n + K - 1) / K) : 0u;
+        const uint32_t np = (n > a.wide_max) ? (uint32_t)((n + K - 1) / K) : 0u;
         wave_append(&a.counters[4], a.pieces, a.cap, a.s.err, np, t, lane);
         for (int r = 0; r < a.rounds; ++r) {
             const uint32_t nr = (n > ((int64_t)K << r)) ? np : 0u;
@@ -227,7 +242,7 @@ TS_DEV void stage_keys(uint32_t* A, const SortArgs& s, int64_t o, int n, int w0,
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const uint32_t i = (uint32_t)(64 * (g + j) + lane);
-            const uint32_t key = (i < (uint32_t)n) ? (s.f32 ? f32_to_ordered(kk[j]) : kk[j]) : 0xFFFFFFFFu;
+            const uint32_t key = ((int)i < n) ? (s.f32 ? f32_to_ordered(kk[j]) : kk[j]) : 0xFFFFFFFFu;
             lds_store(A, (uint32_t)(w0 + (int)i) * 4u, key);
         }
     }
@@ -320,6 +335,36 @@ void merge_sort_kernel(MergeArgs a) {
                 if (r < n) *(uint64_t*)((char*)rb + (uint32_t)r * 8u) = v[c];
             }
         }
+    }
+}
+
+// Workgroup bins (4, 5, 6): one tile of up to 4096 H keys per workgroup of H wavefronts,
+// sorted whole by bitonic_sort_wide; wavefront h loads items 4096 h .. and stores ranks
+// 4096 h .. (keys, permutation and payload).
+template <int H>
+__global__ __launch_bounds__(64 * H) __attribute__((amdgpu_waves_per_eu(2)))
+void merge_wide_kernel(MergeArgs a) {
+    constexpr int BIN = H == 2 ? 4 : H == 4 ? 5 : 6;
+    __shared__ __attribute__((aligned(16))) uint32_t A[wide_bitonic_words<H>()];
+    const int h = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t cnt = uniform(a.counters[bin_counter(BIN)]);
+    for (uint32_t item = blockIdx.x; item < cnt; item += gridDim.x) {
+        const int lane = (int)opaque((uint32_t)lane_id());
+        int64_t o;
+        int n;
+        bin_tile(a, BIN, cnt, item, o, n);
+        const int nw = n > 4096 * h ? n - 4096 * h : 0;  // items of this wavefront's part
+        uint32_t* Aw = A + h * MOVE_WORDS;
+        __syncthreads();  // the previous tile's exchanges are done
+        stage_keys<64>(Aw, a.s, o + 4096 * h, nw, 0, lane);
+        uint64_t v[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const uint32_t i = (uint32_t)(64 * c + lane);
+            v[c] = make_comp(0u, lds_load(Aw, i * 4u), (uint32_t)(4096 * h) + i);
+        }
+        bitonic_sort_wide<H>(A, v, h, lane);
+        store_final_regs<R>(a.s, o, 4096 * h, nw, v, 0, lane, narrow_payload(a));
     }
 }
 
@@ -443,14 +488,16 @@ int rounds_for(int64_t max_len) {
 }  // namespace
 
 void set_merge_pack(int v) { g_merge_pack = v; }
+void set_merge_wide(int v) { g_merge_wide = v; }
 
 MergeLayout merge_layout(int64_t num_tiles, int64_t total_len, int64_t max_len) {
     MergeLayout L{};
-    L.rounds = rounds_for(max_len);
+    // merge rounds only for tiles longer than the workgroup bins take
+    L.rounds = max_len > g_merge_wide ? rounds_for(max_len) : 0;
     L.cap = total_len / K + num_tiles + 1;
     size_t off = 256;  // header: error word and counters
     L.bins = off;
-    off += align256((size_t)num_tiles * 4 * 8);
+    off += align256((size_t)num_tiles * NUM_BINS * 8);
     L.pieces = off;
     off += align256((size_t)L.cap * 8);
     L.round_lists = off;
@@ -484,6 +531,7 @@ hipError_t launch_sort_merge(const SortArgs& s, int64_t total_len, int64_t max_l
     a.pack = g_merge_pack;
     a.max_len = max_len;
     a.total_len = total_len;
+    a.wide_max = g_merge_wide > K ? g_merge_wide : K;
 
     hipError_t e = launch_fill_zero(a.counters, MERGE_COUNTER_BYTES, st);
     if (e != hipSuccess) return e;
@@ -494,7 +542,20 @@ hipError_t launch_sort_merge(const SortArgs& s, int64_t total_len, int64_t max_l
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {
-        // pieces first (the longest chains of work), then the packing bins
+        // the workgroup bins (whole tiles of up to 32768 keys), largest first
+        if (max_len > K && g_merge_wide > K) {
+            hipLaunchKernelGGL(merge_wide_kernel<8>, dim3(persistent_grid((const void*)merge_wide_kernel<8>, 512, 0,
+                                                                          s.num_tiles)),
+                               dim3(512), 0, st, a);
+            hipLaunchKernelGGL(merge_wide_kernel<4>, dim3(persistent_grid((const void*)merge_wide_kernel<4>, 256, 0,
+                                                                          s.num_tiles)),
+                               dim3(256), 0, st, a);
+            hipLaunchKernelGGL(merge_wide_kernel<2>, dim3(persistent_grid((const void*)merge_wide_kernel<2>, 128, 0,
+                                                                          s.num_tiles)),
+                               dim3(128), 0, st, a);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        // pieces (the longest chains of work), then the packing bins
         const void* kinds[5] = {(const void*)merge_sort_kernel<4>, (const void*)merge_sort_kernel<3>,
                                 (const void*)merge_sort_kernel<2>, (const void*)merge_sort_kernel<1>,
                                 (const void*)merge_sort_kernel<0>};

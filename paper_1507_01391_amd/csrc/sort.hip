@@ -32,7 +32,9 @@
 //
 // BITONIC is Batcher's bitonic network on the 4096 items, with the stages on
 // register bits done in registers and the stages on lane bits done in registers
-// after a conflict-free transpose (the same transpose the column sort uses).
+// after a conflict-free transpose (the same transpose the column sort uses); tiles of
+// 8192 and 16384 keys spread the network over 2 and 4 wavefronts, whose stages on the
+// wavefront bits compare through LDS.
 #include "bitonic.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -213,29 +215,6 @@ constexpr int wide_words() {
     return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
-// Compare-exchange of every register with the same register of wavefront hp (same
-// lane): the wavefront with the lower index keeps the smaller composite when `asc`.
-// Sixteen registers at a time go through LDS as 64-bit words, lane L of wavefront h at
-// slot (16 h + j) 64 + L: 16 (writes) or 32 (reads) consecutive 8-byte slots per
-// phase, no bank conflicts.
-template <int H>
-TS_DEV void cross_wave_stage(uint64_t* X, uint64_t (&v)[R], int h, int hp, bool asc, int lane) {
-    const bool keep_min = (h < hp) == asc;
-#pragma unroll
-    for (int g = 0; g < R; g += 16) {
-        __syncthreads();  // earlier readers of X are done
-#pragma unroll
-        for (int j = 0; j < 16; ++j) X[(16 * h + j) * 64 + lane] = v[g + j];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const uint64_t y = X[(16 * hp + j) * 64 + lane];
-            const uint64_t x = v[g + j];
-            v[g + j] = keep_min ? (y < x ? y : x) : (y < x ? x : y);
-        }
-    }
-}
-
 // Ascending sort of every row of m = 64 H items spread over the H wavefronts: a bitonic
 // sort whose stages on register bits run in registers and whose stages on wavefront
 // bits compare across wavefronts.  The caller has sorted each wavefront's 64 registers,
@@ -245,14 +224,14 @@ template <int H>
 TS_DEV void wide_row_merge(uint64_t* X, uint64_t (&v)[R], int h, int lane) {
     // level 128: pairs of wavefronts; with H = 4 the second pair merges descending
     const bool asc128 = (H == 2) || ((h >> 1) & 1) == 0;
-    cross_wave_stage<H>(X, v, h, h ^ 1, asc128, lane);
+    cross_wave_stage(X, v, h, h ^ 1, asc128, lane);
     const uint64_t m2 = asc128 ? 0ull : ~0ull;
     xor_all(v, m2);
     row_merge(v);
     xor_all(v, m2);
     if constexpr (H == 4) {  // level 256
-        cross_wave_stage<H>(X, v, h, h ^ 2, true, lane);
-        cross_wave_stage<H>(X, v, h, h ^ 1, true, lane);
+        cross_wave_stage(X, v, h, h ^ 2, true, lane);
+        cross_wave_stage(X, v, h, h ^ 1, true, lane);
         row_merge(v);
     }
 }
@@ -403,6 +382,75 @@ hipError_t launch_thm2_wide(const SortArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------
+// Batcher's bitonic sort of tiles of 4096 H keys, H = 2 or 4 wavefronts per tile
+// (bitonic_sort_wide): wavefront h loads items 4096 h .. 4096 h + 4095 and stores ranks
+// 4096 h .. 4096 h + 4095.
+template <int H>
+__global__ __launch_bounds__(64 * H) __attribute__((amdgpu_waves_per_eu(2)))
+void bitonic_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
+    constexpr int CAP = 4096 * H;
+    __shared__ __attribute__((aligned(16))) uint32_t A[wide_bitonic_words<H>()];
+    const int h = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int64_t t = blockIdx.x; t < a.num_tiles; t += gridDim.x) {
+        const int lane = (int)opaque((uint32_t)lane_id());
+        const int64_t o = offs[t];
+        const int64_t len = offs[t + 1] - o;
+        if (len > CAP) {
+            if (threadIdx.x == 0) atomicOr(a.err, ERR_TILE_TOO_LONG);
+            continue;
+        }
+        const int n = (int)len;
+        const int nw = n > 4096 * h ? n - 4096 * h : 0;  // items of this wavefront's part
+        // ---- load through this wavefront's own part of A (16 columns in flight)
+        uint32_t* Aw = A + h * MOVE_WORDS;
+        __syncthreads();  // every wavefront is done with the previous tile's exchanges
+#pragma unroll 1
+        for (int g = 0; g < R; g += 16) {
+            uint32_t kk[16];
+            load_columns<16>(a.keys_in, 1, o + 4096 * h, nw, g, lane, kk, offs);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int i = 64 * (g + j) + lane;
+                lds_store(Aw, (uint32_t)i * 4u, (i < nw) ? (a.f32 ? f32_to_ordered(kk[j]) : kk[j]) : 0xFFFFFFFFu);
+            }
+        }
+        uint64_t v[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c)
+            v[c] = pack(lds_load(Aw, (uint32_t)(64 * c + lane) * 4u), (uint32_t)(4096 * h + 64 * c + lane));
+
+        bitonic_sort_wide<H>(A, v, h, lane);
+
+        // ---- store: register c of lane L in wavefront h holds rank 4096 h + 64 c + L
+        const int sl = (int)opaque((uint32_t)lane);
+        const int rb = 4096 * h;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int r = rb + 64 * c + sl;
+            if (r < n) {
+                const uint32_t key = hi32(v[c]);
+                if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
+                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)lo32(v[c]));
+            }
+        }
+        if (a.fuse_pay) {
+            uint32_t pos[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) pos[c] = lo32(v[c]);
+            gather_payload<R>(a, o, n, pos, lane, [rb](int c, int ln) { return rb + 64 * c + ln; });
+        }
+    }
+}
+
+template <int H>
+hipError_t launch_bitonic_wide(const SortArgs& a, hipStream_t s) {
+    auto kern = bitonic_wide_kernel<H>;
+    const int grid = persistent_grid((const void*)kern, 64 * H, 0, a.num_tiles);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * H), 0, s, a, a.offsets);
+    return hipGetLastError();
+}
+
 template <int SCHED>
 hipError_t launch_s4096(const SortArgs& a, hipStream_t s) {
     auto kern = sort4096_kernel<SCHED>;
@@ -413,7 +461,7 @@ hipError_t launch_s4096(const SortArgs& a, hipStream_t s) {
 
 }  // namespace
 
-int64_t sort_capacity(int sched) { return sched == 3 ? 4096 : 16384; }
+int64_t sort_capacity(int sched) { (void)sched; return 16384; }
 
 hipError_t launch_sort(const SortArgs& a, int64_t max_len, int sched, hipStream_t s) {
     if (a.num_tiles == 0) return hipSuccess;
@@ -422,7 +470,11 @@ hipError_t launch_sort(const SortArgs& a, int64_t max_len, int sched, hipStream_
         if (max_len <= 8192) return launch_thm2_wide<2>(a, s);
         return launch_thm2_wide<4>(a, s);
     }
-    if (sched == 3) return launch_s4096<3>(a, s);
+    if (sched == 3) {
+        if (max_len <= 4096) return launch_s4096<3>(a, s);
+        if (max_len <= 8192) return launch_bitonic_wide<2>(a, s);
+        return launch_bitonic_wide<4>(a, s);
+    }
     return launch_sort_split(a, max_len, s);
 }
 

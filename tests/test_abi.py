@@ -41,11 +41,15 @@ def test_version_and_workspace_size(lib):
     # the merge schedule keeps two runs of 8-byte composites plus work lists
     merge = 4 << 8
     n, tiles = 1 << 20, 64
-    assert lib.ts_workspace_bytes(0, merge, tiles, n, 32768, 1) >= 16 * n
+    assert lib.ts_workspace_bytes(0, merge, tiles, n, 65536, 1) >= 16 * n
     # AUTO takes the merge schedule beyond 16384 keys per tile
     assert lib.ts_workspace_bytes(0, 0, tiles, n, 32768, 0) == lib.ts_workspace_bytes(0, merge, tiles, n, 32768, 0)
-    # a single piece per tile needs no runs
+    assert lib.ts_workspace_bytes(0, 0, tiles, n, 65536, 0) == lib.ts_workspace_bytes(0, merge, tiles, n, 65536, 0)
+    # a single piece per tile needs no runs, and neither do tiles sorted whole by one
+    # workgroup (up to 32768 keys)
     assert lib.ts_workspace_bytes(0, merge, tiles, n, 4096, 0) < 2 * n
+    assert lib.ts_workspace_bytes(0, merge, tiles, n, 32768, 0) < 2 * n
+    assert lib.ts_workspace_bytes(0, merge, tiles, n, 32769, 0) >= 16 * n
 
 
 def _err(lib):
@@ -75,7 +79,7 @@ def test_partition_argument_validation(lib):
     thm2, bitonic, naive = 2 << 8, 3 << 8, 15 << 8
     rc = lib.tile_partition(fake, P(0x3000), None, None, 0, 1, 0, 64, None, fake, 1, 16385, thm2, ws, 256, None)
     assert rc == 2
-    rc = lib.tile_partition(fake, P(0x3000), None, None, 0, 1, 0, 64, None, fake, 1, 8192, bitonic, ws, 256, None)
+    rc = lib.tile_partition(fake, P(0x3000), None, None, 0, 1, 0, 64, None, fake, 1, 16385, bitonic, ws, 256, None)
     assert rc == 2
     # the naive baseline moves one payload channel; the other schedules any number
     rc = lib.tile_partition(fake, P(0x3000), fake, P(0x4000), 2, 1, 4096, 64, None, fake, 1, 4096, naive, ws,
@@ -97,8 +101,8 @@ def test_sort_argument_validation(lib):
     # aliasing
     rc = lib.tile_sort(fake, fake, None, None, 0, 1, 0, None, fake, 1, 4096, 4096, 0, ws, 256, None)
     assert rc == 1 and "alias" in _err(lib)
-    # the bitonic schedule holds 4096 keys per tile, Theorem 2 16384
-    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 8192, 8192, 3 << 8, ws, 256, None)
+    # the bitonic and Theorem 2 schedules hold 16384 keys per tile
+    rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 16385, 16385, 3 << 8, ws, 256, None)
     assert rc == 2
     rc = lib.tile_sort(fake, P(0x3000), None, None, 0, 1, 0, None, fake, 1, 16385, 16385, 2 << 8, ws, 256, None)
     assert rc == 2
@@ -115,9 +119,13 @@ def test_sort_argument_validation(lib):
 
 
 def test_tune_knob_validation(lib):
-    assert lib.ts_tune(b"sort_plan_8192", 3) == 1          # bitonic cannot hold 8192 keys
-    assert lib.ts_tune(b"sort_plan_16384", 2) == 0         # Theorem 2 can
+    assert lib.ts_tune(b"sort_plan_8192", 3) == 0          # bitonic and Theorem 2 hold 16384 keys
+    assert lib.ts_tune(b"sort_plan_16384", 2) == 0
     assert lib.ts_tune(b"sort_plan_16384", 4) == 0
+    assert lib.ts_tune(b"sort_plan_8192", 4) == 0
+    assert lib.ts_tune(b"sort_plan_8192", 5) == 1          # no such schedule
+    assert lib.ts_tune(b"merge_wide", 12288) == 1
+    assert lib.ts_tune(b"merge_wide", 32768) == 0
     assert lib.ts_tune(b"sort_plan_4096", 7) == 1
     assert lib.ts_tune(b"merge_pack", 2) == 1
     assert lib.ts_tune(b"no_such_knob", 0) == 1

@@ -78,7 +78,7 @@ def test_f32_keys_with_special_values(ts, oracle, schedule):
     run_and_compare(ts, oracle, x.view(np.uint32), payload.view(np.uint32), off, schedule, f32=True)
 
 
-@pytest.mark.parametrize("schedule", ["split", "naive", "auto", "merge", "thm2"])
+@pytest.mark.parametrize("schedule", ["split", "naive", "auto", "merge", "thm2", "bitonic"])
 @pytest.mark.parametrize("cap", [8192, 16384])
 def test_large_tiles(ts, oracle, schedule, cap):
     rng = np.random.default_rng(cap)
@@ -98,24 +98,29 @@ def test_segments_workload_sample(ts, oracle):
 # ---- merge schedule: tiles longer than one workgroup, packing of short tiles --------
 
 EDGE_SIZES = [0, 1, 2, 63, 64, 65, 511, 512, 513, 1024, 1025, 2048, 2049, 4095, 4096, 4097,
-              8191, 8192, 8193, 12289, 16384, 16385, 20000, 32767, 32768]
+              8191, 8192, 8193, 12289, 16384, 16385, 20000, 32767, 32768, 32769, 40000, 65536]
 
 
-@pytest.mark.parametrize("pack", [1, 0])
-def test_merge_edge_sizes(ts, oracle, pack):
-    rng = np.random.default_rng(21 + pack)
+@pytest.mark.parametrize("pack,wide", [(1, 32768), (0, 32768), (1, 4096), (1, 8192), (0, 16384)])
+def test_merge_edge_sizes(ts, oracle, pack, wide):
+    """Tile lengths at every bin edge; with merge_wide = 4096 every tile above 4096 keys
+    goes through pieces and merge rounds, with 32768 (the default) tiles up to 32768 keys
+    are sorted whole by one workgroup and only the longer ones are merged."""
+    rng = np.random.default_rng(21 + pack + wide)
     sizes = np.array(EDGE_SIZES)
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     keys = rng.integers(0, 50, size=off[-1], dtype=np.uint32)           # heavy ties
     keys[::5] = rng.integers(0, 2**32, size=keys[::5].shape[0], dtype=np.uint32)
     payload = np.stack([np.arange(off[-1], dtype=np.uint32),
                         rng.integers(0, 2**32, size=off[-1], dtype=np.uint32)])
-    prev = ts.knob("merge_pack", 1)
+    prev, prev_w = ts.knob("merge_pack", 1), ts.knob("merge_wide", 32768)
     ts.tune("merge_pack", pack)
+    ts.tune("merge_wide", wide)
     try:
-        run_and_compare(ts, oracle, keys, payload, off, "merge", max_len=32768)
+        run_and_compare(ts, oracle, keys, payload, off, "merge", max_len=65536)
     finally:
         ts.tune("merge_pack", prev)
+        ts.tune("merge_wide", prev_w)
 
 
 @pytest.mark.parametrize("seed", [11, 12])
