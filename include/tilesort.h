@@ -229,6 +229,36 @@ ts_status ts_device_partition(const uint32_t* labels_in, uint32_t* labels_out,
                               int64_t n, uint32_t num_classes, uint32_t flags, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* Bits of the device error word: ts_check reports them, tile_sort_noalloc ORs them
+   into its err_out word. */
+enum {
+    TS_ERRBIT_TILE_TOO_LONG = 1u, /* a tile was longer than max_tile_len (skipped) */
+    TS_ERRBIT_BAD_LABEL = 2u,     /* TS_FLAG_VALIDATE: a label >= num_classes */
+    TS_ERRBIT_BAD_PERM = 4u,      /* TS_FLAG_VALIDATE: pi is not a permutation of its tile */
+    TS_ERRBIT_BAD_OFFSETS = 8u    /* a tile outside [0, total_len) (skipped) */
+};
+
+/*
+ * tile_sort_noalloc -- tile_sort for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, results and schedules as tile_sort, but no workspace.  Its scratch
+ * (error word, work counters and lists, the permutation of a payload without perm_out)
+ * is a static 32 MiB device array in the library, one per GPU, kept until the process
+ * ends.  The call allocates nothing and enqueues only kernels (capturable).
+ *   err_out : optional device uint32; the call ORs the TS_ERRBIT_* bits of the
+ *             contract violations it met into it (the caller clears it).
+ * Returns TS_ERR_WORKSPACE when ts_workspace_bytes(TS_OP_SORT, flags, ...) for these
+ * sizes exceeds 32 MiB (e.g. the merge schedule with tiles above 32768 keys, whose runs
+ * take 16 bytes per key), else what tile_sort returns.  Every call on one GPU shares
+ * the array: calls that overlap in time on one GPU (two streams, two threads) race and
+ * must be ordered by the caller.
+ */
+ts_status tile_sort_noalloc(const uint32_t* keys_in, uint32_t* keys_out,
+                            const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
+                            int64_t elem_stride, int64_t chan_stride, int32_t* perm_out,
+                            const int64_t* tile_offsets, int64_t num_tiles, int64_t total_len,
+                            int64_t max_tile_len, uint32_t flags, uint32_t* err_out, void* stream);
+
 /* Bytes of workspace a call of operation `op` (TS_OP_*) with these flags and sizes
    needs (never 0).  total_len is the number of items (tile_offsets[num_tiles]). */
 size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t total_len,

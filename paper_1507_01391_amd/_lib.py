@@ -25,6 +25,7 @@ EXPORTS = (
     "tile_sort", "tile_partition", "tile_permute", "ts_device_sort", "ts_device_partition",
     "ts_workspace_bytes", "ts_workspace_init",
     "ts_check", "ts_last_error", "ts_version", "ts_copy", "ts_lds_probe", "ts_tune",
+    "tile_sort_noalloc",
 )
 
 
@@ -54,6 +55,8 @@ def load() -> ctypes.CDLL:
     S = ctypes.c_int
     lib.tile_sort.argtypes = [P, P, P, P, U32, I64, I64, P, P, I64, I64, I64, U32, P, SZ, P]
     lib.tile_partition.argtypes = [P, P, P, P, U32, I64, I64, U32, P, P, I64, I64, U32, P, SZ, P]
+    lib.tile_sort_noalloc.argtypes = [P, P, P, P, U32, I64, I64, P, P, I64, I64, I64, U32, P, P]
+    lib.tile_sort_noalloc.restype = S
     lib.tile_permute.argtypes = [P, P, U32, I64, I64, P, U32, P, P, I64, I64, U32, P, SZ, P]
     lib.ts_device_sort.argtypes = [P, P, P, P, P, I64, U32, P, SZ, P]
     lib.ts_device_partition.argtypes = [P, P, P, P, P, I64, U32, U32, P, SZ, P]

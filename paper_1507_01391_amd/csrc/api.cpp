@@ -32,6 +32,10 @@ ts_status hip_status(hipError_t e, const char* what) {
     return fail(TS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+static_assert(TS_ERRBIT_TILE_TOO_LONG == ts::ERR_TILE_TOO_LONG && TS_ERRBIT_BAD_LABEL == ts::ERR_BAD_LABEL &&
+                  TS_ERRBIT_BAD_PERM == ts::ERR_BAD_PERM && TS_ERRBIT_BAD_OFFSETS == ts::ERR_BAD_OFFSETS,
+              "the error bits of the C interface are the kernels' bits");
+
 // Workspace layout: word 0 = error bits; words 1..63 reserved (counters); 256 bytes total.
 constexpr size_t kWorkspaceBytes = 256;
 
@@ -87,6 +91,11 @@ ts_status check_payload(const uint32_t* in, const uint32_t* out, uint32_t channe
 }  // namespace
 
 namespace ts {
+
+int set_error(int st, const char* msg) {
+    g_last_error = msg;
+    return st;
+}
 
 int num_cus() {
     static int cus = [] {

@@ -6,7 +6,7 @@
 
 namespace ts {
 
-// Bits of the workspace error word.
+// Bits of the workspace error word (the TS_ERRBIT_* values of tilesort.h).
 enum : uint32_t {
     ERR_TILE_TOO_LONG = 1u,   // a tile exceeded the kernel's capacity and was skipped
     ERR_BAD_LABEL = 2u,       // TS_FLAG_VALIDATE: label >= num_classes
@@ -156,6 +156,8 @@ void set_merge_wide(int v);
 
 // Device properties cached by the API layer.
 int num_cus();
+// Record `msg` as the thread's last error message and return st (a ts_status).
+int set_error(int st, const char* msg);
 
 // Each returns hipSuccess or the launch error.  `cap` is the kernel's tile capacity.
 hipError_t launch_partition_split(const PartitionArgs& a, int64_t max_len, hipStream_t s);
