@@ -28,16 +28,47 @@ METRIC = "sorted uint32 keys/s per GPU + LDS bank conflicts/access; fwd+bwd perm
 PARTITION_BYTES_PER_KEY = 16
 # Permutation, per direction: value in + pi in + value out.
 PERMUTE_BYTES_PER_ELEM = 12
+# LDS bytes per key of the partition kernel: six binary splits, each writing and reading
+# every 8-byte item once.
+PARTITION_LDS_BYTES_PER_KEY = 6 * 2 * 8
+# Uneven segmented sort: keys in and out, payload word in and out.
+SEGMENTS_BYTES_PER_KEY = 16
+# Differentiable sort-with-payload, 8 channels, per key: forward keys in + sorted keys
+# out + permutation out + payload in + payload out (4 + 4 + 4 + 32 + 32), backward
+# gradient of the payload in + permutation in + gradient out (32 + 4 + 32).
+SORT_PAYLOAD_BYTES_PER_KEY = 144
 
 
-# HBM bytes per launch of the partition kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE,
-# scaled by the same counters on a 1 GiB copy (profiles/partition_split_c2_traffic.md),
-# for the default 65536-tile workload.  Reported only while the kernel sources are the
-# ones that were measured and the measured variant is selected.
-MEASURED_TRAFFIC = {"bytes_per_launch": 4.3034e9, "tiles": 65536, "partition_waves_4096": 168,
-                    "sources": ["paper_1507_01391_amd/csrc/partition.hip",
-                                "paper_1507_01391_amd/csrc/common.hpp"],
-                    "sha256_prefix": "4f7dd570a58a8135"}
+NUM_CUS = 256                   # MI355X compute units
+CLOCK_HZ = 2.4e9                # MI355X peak engine clock
+# LDS bandwidth ceiling per CU: 256 bytes per clock, what a conflict-free 64-bit read
+# of 64 lanes delivers in its two cycles (a 32-bit access moves half of it, a 64-bit
+# write takes four cycles; profiles/lds_bank_model.md); 256 CUs x 256 B x 2.4 GHz.
+LDS_PEAK_GBPS = NUM_CUS * 256 * CLOCK_HZ / 1e9
+
+# Counters per step of each workload, from rocprofv3 runs of the profile_run workloads
+# (profiles/*_counters.md), each valid only while the listed sources are the ones that
+# were measured.  fetch/write: HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by the same
+# counters on a 1 GiB copy; lds_*: SQ_INSTS_LDS, SQ_LDS_IDX_ACTIVE (LDS busy cycles summed
+# over CUs) and SQ_LDS_BANK_CONFLICT summed over the step's dispatches.
+KSRC = "paper_1507_01391_amd/csrc/"
+MEASURED = {
+    "c2": {"profile": "profiles/partition_split_c2_counters.md",
+           "sources": [KSRC + "partition.hip", KSRC + "common.hpp"],
+           "sha256_prefix": None, "knobs": {"partition_waves_4096": 168}},
+    "c3": {"profile": "profiles/permute_c3_counters.md",
+           "sources": [KSRC + "permute.hip", KSRC + "route.hpp", KSRC + "common.hpp"],
+           "sha256_prefix": None, "knobs": {}},
+    "c4": {"profile": "profiles/merge_c4_counters.md",
+           "sources": [KSRC + "merge.hip", KSRC + "bitonic.hpp", KSRC + "common.hpp"],
+           "sha256_prefix": "24a8ade22f7f8218", "knobs": {"merge_wide": 32768},
+           "fetch": 2807199 * 2 * 1024, "write": 8178874 * 1024,
+           "lds_insts": 582923358, "lds_active": 2533340340, "lds_conflicts": 0},
+    "c5": {"profile": "profiles/sort_payload_c5_counters.md",
+           "sources": [KSRC + "partition.hip", KSRC + "permute.hip", KSRC + "route.hpp", KSRC + "common.hpp",
+                       "paper_1507_01391_amd/autograd.py", "paper_1507_01391_amd/plans/gfx950.json"],
+           "sha256_prefix": None, "knobs": {}},
+}
 
 
 def sources_hash(paths):
@@ -49,14 +80,39 @@ def sources_hash(paths):
     return h.hexdigest()
 
 
-def measured_traffic(tiles, ts):
-    m = MEASURED_TRAFFIC
-    if m["bytes_per_launch"] is None or not m["sha256_prefix"]:
+def measured(name, ts):
+    """The counter record of a workload, or None when its kernels' sources (or tuned
+    knobs) differ from the ones that were measured."""
+    m = MEASURED[name]
+    if not m.get("sha256_prefix") or not sources_hash(m["sources"]).startswith(m["sha256_prefix"]):
         return None
-    same = sources_hash(m["sources"]).startswith(m["sha256_prefix"])
-    if same and tiles == m["tiles"] and ts.knob("partition_waves_4096", 168) == m["partition_waves_4096"]:
-        return m["bytes_per_launch"]
-    return None
+    for k, v in m["knobs"].items():
+        if ts.knob(k, v) != v:
+            return None
+    return m
+
+
+def roofline(bytes_per_unit, units, mean_ms, rec, lds_bytes_per_unit=None):
+    """HBM roofline of one step (algorithmic bytes over its mean duration against the
+    8 TB/s peak), with the measured traffic and LDS figures of `rec` when valid."""
+    algo = bytes_per_unit * units
+    achieved = algo / (mean_ms / 1e3) / 1e9
+    r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+         "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "algorithmic_bytes": algo,
+         "bytes_per_unit": bytes_per_unit, "kernel_mean_ms": mean_ms, "lds": None}
+    if rec is not None:
+        r["traffic"] = rec["fetch"] + rec["write"]
+        t = mean_ms / 1e3
+        lds = {"conflict_cycles_per_lds_instruction": rec["lds_conflicts"] / rec["lds_insts"],
+               "conflict_cycles_per_busy_cycle": rec["lds_conflicts"] / rec["lds_active"],
+               "busy_frac": rec["lds_active"] / (NUM_CUS * CLOCK_HZ * t),
+               "profile": rec["profile"]}
+        if lds_bytes_per_unit is not None:
+            lb = lds_bytes_per_unit * units / t / 1e9
+            lds.update({"achieved": lb, "peak": LDS_PEAK_GBPS, "unit": "GB/s", "frac": lb / LDS_PEAK_GBPS,
+                        "bytes_per_unit": lds_bytes_per_unit})
+        r["lds"] = lds
+    return r
 
 
 def log(msg):
@@ -83,23 +139,34 @@ def timed_launches(fn, steps, warmup, torch):
     return wall_ms, float(np.mean(per)), per
 
 
-def cpu_baseline_partition(labels, payload, offsets, oracle, min_seconds=10.0):
-    """Time the oracle on a bounded sample of tiles; returns (keys/s, cores, sample text)."""
-    cores = min(os.cpu_count() or 1, 16)
-    tiles = min(16384, len(offsets) - 1)
-    n = int(offsets[tiles])
-    lab = np.ascontiguousarray(labels[:n])
-    pay = np.ascontiguousarray(payload[:n].view(np.uint32))
-    off = np.ascontiguousarray(offsets[:tiles + 1])
+def host_threads():
+    """Threads for the oracle's multi-threaded run: the CPUs this process may use, at most
+    16 (the host CPU share of one GPU on these machines); and the CPUs visible."""
+    vis = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(vis, 16)), vis
+
+
+def time_cpu(fn, units, min_seconds):
+    """Repeat fn() for at least min_seconds; returns (units per second, repetitions, s)."""
     reps = 0
     t0 = time.perf_counter()
     while True:
-        oracle.tile_partition(lab, pay, off, num_classes=64, nthreads=cores)
+        fn()
         reps += 1
         el = time.perf_counter() - t0
-        if el >= min_seconds or reps >= 2000:
+        if el >= min_seconds:
             break
-    return n * reps / el, cores, f"{tiles} of {len(offsets) - 1} tiles ({n} keys), {reps} repetitions, {el:.1f} s"
+    return units * reps / el, reps, el
+
+
+def cpu_baseline(run, units, unit, sample, min_seconds):
+    """The oracle on a bounded sample, single-threaded and on the host threads."""
+    T, vis = host_threads()
+    v1, r1, e1 = time_cpu(lambda: run(1), units, min_seconds / 2)
+    vT, rT, eT = time_cpu(lambda: run(T), units, min_seconds / 2)
+    return {"value": vT, "unit": unit, "cores": T, "kind": "oracle", "sample": sample,
+            "single_thread_value": v1, "host_cpus_visible": vis,
+            "timing": f"{rT} repetitions in {eT:.1f} s on {T} threads, {r1} in {e1:.1f} s on 1"}
 
 
 def bench_c2(args, torch, ts, inputs):
@@ -123,7 +190,8 @@ def bench_c2(args, torch, ts, inputs):
     ts.check_device_errors()
     ms_per_step = wall_ms / args.steps
     value = n_total / (ms_per_step / 1e3)
-    achieved = PARTITION_BYTES_PER_KEY * n_total / (mean_ms / 1e3) / 1e9
+    rec = measured("c2", ts) if T == 65536 else None
+    roof = roofline(PARTITION_BYTES_PER_KEY, n_total, mean_ms, rec, PARTITION_LDS_BYTES_PER_KEY)
 
     # parity on sampled tiles (oracle computes them one by one)
     from oracle import oracle as orc
@@ -179,16 +247,21 @@ def bench_c2(args, torch, ts, inputs):
         # secondary workloads: single-tile latency, fwd+bwd permutation, uneven
         # segmented sort (graph replay), differentiable sort with an 8-channel payload
         extra.update(bench_c1(torch, ts, inputs))
-        extra.update(bench_c3(args, torch, ts, inputs))
-        extra.update(bench_c4(args, torch, ts, inputs, orc))
-        extra.update(bench_c5(args, torch, ts, inputs))
+        extra["c3_permute_fwd_bwd"] = bench_c3(args, torch, ts, inputs, orc)
+        extra["c4_segmented_sort"] = bench_c4(args, torch, ts, inputs, orc)
+        extra["c5_sort_with_payload"] = bench_c5(args, torch, ts, inputs, orc)
         extra.update(bench_device_sort(torch, ts))
 
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample ...")
-        v, cores, sample_txt = cpu_baseline_partition(labels, payload, offsets, orc)
-        cpu = {"value": v, "unit": "keys/s", "cores": cores, "kind": "oracle", "sample": sample_txt}
+        tiles = min(8192, T)
+        n = int(offsets[tiles])
+        lab = np.ascontiguousarray(labels[:n])
+        pay = np.ascontiguousarray(payload[:n].view(np.uint32))
+        off = np.ascontiguousarray(offsets[:tiles + 1])
+        cpu = cpu_baseline(lambda th: orc.tile_partition(lab, pay, off, num_classes=64, nthreads=th), n,
+                           "keys/s", f"{tiles} of {T} tiles ({n} keys, labels and payload)", args.cpu_seconds)
 
     return {
         "metric": METRIC,
@@ -208,11 +281,7 @@ def bench_c2(args, torch, ts, inputs):
                                "1-channel fp32 payload N(0,1)",
                    "tiles": T, "tile_len": 4096, "num_classes": 64, "payload_channels": 1,
                    "kernel": "partition_split (alternating-direction binary splits)"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": measured_traffic(T, ts),
-                     "bytes_per_key": PARTITION_BYTES_PER_KEY,
-                     "kernel_mean_ms": mean_ms},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,
     }
@@ -234,7 +303,7 @@ def bench_c1(torch, ts, inputs):
     return out
 
 
-def bench_c3(args, torch, ts, inputs):
+def bench_c3(args, torch, ts, inputs, orc):
     """fwd + bwd permutation of 16384 tiles x 8192 fp32: forward y[pi[i]] = x[i], backward
     dx[i] = dy[pi[i]] -- the conflict-free path writes pi^-1 (16-bit tile-local indices;
     "inv32": int32) during the forward routing and runs the backward as a scatter by it
@@ -251,7 +320,7 @@ def bench_c3(args, torch, ts, inputs):
     inv = torch.empty(dpi.shape, dtype=torch.int16, device=dpi.device)
     inv32 = torch.empty_like(dpi)
     n = T * 8192
-    out = {}
+    variants_out = {}
 
     def split_fwd_bwd():
         ts.tile_permute(dx, dpi, "scatter", doff, max_tile_len=8192, out=y, inv_out=inv)
@@ -278,11 +347,13 @@ def bench_c3(args, torch, ts, inputs):
         for _ in range(3):
             fn()
     torch.cuda.synchronize()
+    means = {}
     for name, fn in variants:
         ts.tune("naive_oneshot", 1 if name == "naive_oneshot" else 0)
         log(f"[bench] C3 fwd+bwd permute ({name}) ...")
         w, m, _ = timed_launches(fn, 10, 3, torch)
-        out[f"c3_permute_fwd_bwd_GBps_{name}"] = 2 * PERMUTE_BYTES_PER_ELEM * n / (m / 1e3) / 1e9
+        means[name] = m
+        variants_out[name] = 2 * PERMUTE_BYTES_PER_ELEM * n / (m / 1e3) / 1e9
     ts.tune("naive_oneshot", 0)
     # parity of the conflict-free fwd + bwd on sampled tiles
     split_fwd_bwd()
@@ -295,9 +366,28 @@ def bench_c3(args, torch, ts, inputs):
         want_y[p] = x[a:b]
         ok &= bool(np.array_equal(yh[a:b].view(np.uint32), want_y.view(np.uint32)) and
                    np.array_equal(gh[a:b].view(np.uint32), g[a:b][p].view(np.uint32)))
-    out["c3_parity_sampled_tiles"] = "8 tiles bit-exact" if ok else "MISMATCH"
-    out["c3_tiles"] = T
-    del dx, dpi, dg, y, gx, inv
+    out = {"metric": "fwd+bwd permute GB/s (24 B per element)", "value": variants_out["split"],
+           "unit": "GB/s", "workload": f"{T} tiles x 8192 fp32, uniform random pi per tile",
+           "roofline": roofline(2 * PERMUTE_BYTES_PER_ELEM, n, means["split"],
+                                measured("c3", ts) if T == 16384 else None),
+           "variants_GBps": variants_out,
+           "naive_best_GBps": max(variants_out["naive"], variants_out["naive_oneshot"]),
+           "parity_sampled_tiles": "8 tiles bit-exact" if ok else "MISMATCH"}
+    del dx, dpi, dg, y, gx, inv, inv32
+    if not args.no_cpu:
+        log("[bench] C3 oracle ...")
+        tiles = min(1024, T)
+        m = tiles * 8192
+        xs, ps, gs, os_ = x[:m].view(np.uint32), pi[:m], g[:m].view(np.uint32), off[:tiles + 1]
+
+        def run(th):
+            orc.tile_permute(xs, ps, orc.SCATTER, os_, nthreads=th)
+            orc.tile_permute(gs, ps, orc.GATHER, os_, nthreads=th)
+        cb = cpu_baseline(run, m, "elements/s", f"{tiles} of {T} tiles, scatter + gather", args.cpu_seconds / 2)
+        for k in ("value", "single_thread_value"):
+            cb[k] = cb[k] * 2 * PERMUTE_BYTES_PER_ELEM / 1e9
+        cb["unit"] = "GB/s"
+        out["cpu_baseline"] = cb
     return out
 
 
@@ -320,15 +410,25 @@ def bench_c4(args, torch, ts, inputs, orc):
     rng = np.random.default_rng(1)
     ok = True
     kh, ph = ko.cpu().numpy().view(np.uint32), po.cpu().numpy().view(np.uint32)
-    for s in np.sort(rng.choice(S, size=min(16, S), replace=False)):
-        a, b = int(off[s]), int(off[s + 1])
+    for s_ in np.sort(rng.choice(S, size=min(16, S), replace=False)):
+        a, b = int(off[s_]), int(off[s_ + 1])
         wk, wp, _ = orc.tile_sort(keys[a:b], payload[a:b])
         ok &= bool(np.array_equal(kh[a:b], wk) and np.array_equal(ph[a:b], wp))
-    out = {"c4_segmented_sort_keys_per_s": n / (m / 1e3),
-           "c4_GBps_16B_per_key": 16 * n / (m / 1e3) / 1e9,
-           "c4_ms_per_replay": m, "c4_keys": n, "c4_segments": S,
-           "c4_parity_sampled_segments": "16 segments bit-exact" if ok else "MISMATCH"}
+    out = {"metric": "sorted uint32 keys/s", "value": n / (m / 1e3), "unit": "keys/s",
+           "workload": f"{S} segments of 256..32768 keys (log-uniform), {n} keys, 5 key distributions, "
+                       "uint32 index payload, one captured graph replay",
+           "ms_per_replay": m, "keys": n, "segments": S,
+           "roofline": roofline(SEGMENTS_BYTES_PER_KEY, n, m, measured("c4", ts) if S == 100000 else None),
+           "parity_sampled_segments": "16 segments bit-exact" if ok else "MISMATCH"}
     del g, dk, dp, do, ko, po, pm
+    if not args.no_cpu:
+        log("[bench] C4 oracle ...")
+        segs = min(4000, S)
+        m_ = int(off[segs])
+        ks, ps, os_ = keys[:m_], payload[:m_], off[:segs + 1]
+        out["cpu_baseline"] = cpu_baseline(lambda th: orc.tile_sort(ks, ps, os_, nthreads=th), m_, "keys/s",
+                                           f"the first {segs} of {S} segments ({m_} keys, with payload)",
+                                           args.cpu_seconds / 2)
     return out
 
 
@@ -371,7 +471,7 @@ def bench_device_sort(torch, ts, n=1 << 28):
     return out
 
 
-def bench_c5(args, torch, ts, inputs):
+def bench_c5(args, torch, ts, inputs, orc):
     """Differentiable sort-with-payload: rows x 16384 fp32 keys, 8-channel planar fp32
     payload; forward (sort + gather) and backward (scatter of both gradients)."""
     R = args.rows5
@@ -390,8 +490,24 @@ def bench_c5(args, torch, ts, inputs):
     log("[bench] C5 sort-with-payload fwd+bwd ...")
     w, m, _ = timed_launches(step, 5, 2, torch)
     n = R * 16384
-    return {"c5_fwd_bwd_keys_per_s": n / (m / 1e3), "c5_fwd_bwd_GBps_144B_per_key": 144 * n / (m / 1e3) / 1e9,
-            "c5_ms_per_step": m, "c5_rows": R}
+    out = {"metric": "sort-with-payload fwd+bwd keys/s", "value": n / (m / 1e3), "unit": "keys/s",
+           "workload": f"{R} rows x 16384 fp32 keys, 8-channel planar fp32 payload, forward + backward",
+           "ms_per_step": m, "rows": R,
+           "roofline": roofline(SORT_PAYLOAD_BYTES_PER_KEY, n, m, measured("c5", ts) if R == 4096 else None)}
+    del dk, dp, dg, gk
+    if not args.no_cpu:
+        log("[bench] C5 oracle ...")
+        rows = min(128, R)
+        m_ = rows * 16384
+        ks, ps, gs, os_ = keys[:m_], payload[:, :m_], grad[:, :m_], off[:rows + 1]
+
+        def run(th):
+            _, _, perm = orc.tile_sort(ks, ps, os_, f32_ordered=True, nthreads=th)
+            orc.tile_permute(gs, perm, orc.SCATTER, os_, nthreads=th)
+        out["cpu_baseline"] = cpu_baseline(run, m_, "keys/s",
+                                           f"{rows} of {R} rows: sort with the 8-channel payload, then the "
+                                           "scatter of the 8-channel gradient", args.cpu_seconds / 2)
+    return out
 
 
 def main():
@@ -405,6 +521,8 @@ def main():
     ap.add_argument("--rows5", type=int, default=4096)
     ap.add_argument("--config", default="c2", choices=["c2"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="seconds of oracle time per CPU baseline (half single-threaded)")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB copy kernel (reference for HBM traffic counters)")

@@ -118,13 +118,14 @@ enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2, TS_OP_DEVICE_SORT
  *   total_len           : N = tile_offsets[num_tiles], the length of the flat arrays;
  *                         every tile must lie in [0, N).  The merge schedule places its
  *                         runs in the workspace by it and skips (and flags) a tile
- *                         outside [0, N); the other schedules keep the permutation of a
- *                         payload without perm_out at workspace index = item index.
+ *                         outside [0, N); with a payload the other schedules keep the
+ *                         inverse permutation (NAIVE: the permutation) at workspace
+ *                         index = item index and move the payload by it.
  * Supported tile length: 16384 for BITONIC, THM2, SPLIT and NAIVE, 2^28 for MERGE; a longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the
  * autotuned plan for max_tile_len up to 4096 / 8192 / 16384 and MERGE beyond.
  * The workspace must hold ts_workspace_bytes(TS_OP_SORT, flags, ...) bytes: the
  * merge schedule needs about 16 bytes per key for its runs and work lists, a payload
- * without perm_out 4 bytes per key for the permutation.
+ * (outside the merge schedule) 4 bytes per key.
  */
 ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out,
                     const uint32_t* payload_in, uint32_t* payload_out, uint32_t channels,
@@ -162,6 +163,10 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
  *   TS_SCATTER: out[pi[i]] = in[i];   TS_GATHER: out[i] = in[pi[i]].
  * in / out use the payload addressing above with `channels` words per item
  * (channels may be 0 when only inv_out is wanted).
+ *   aux_in / aux_out : optional extra channel (uint32 [N] each, unit stride, both or
+ *             neither), moved by the same routing as the payload: e.g. the gradient
+ *             of the keys beside the gradients of a multi-channel payload.  Not with
+ *             TS_SCHED_NAIVE (TS_ERR_UNSUPPORTED).
  *   inv_out : optional int32 [N]: receives the tile-local inverse permutation,
  *             inv_out[pi[i]] = i, computed by the same routing (no extra pass);
  *             a later GATHER by pi equals a SCATTER by inv_out, which routes once
@@ -172,6 +177,7 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
  */
 ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels,
                        int64_t elem_stride, int64_t chan_stride,
+                       const uint32_t* aux_in, uint32_t* aux_out,
                        const int32_t* pi, uint32_t direction, int32_t* inv_out,
                        const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
                        uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);

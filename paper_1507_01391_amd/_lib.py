@@ -57,7 +57,7 @@ def load() -> ctypes.CDLL:
     lib.tile_partition.argtypes = [P, P, P, P, U32, I64, I64, U32, P, P, I64, I64, U32, P, SZ, P]
     lib.tile_sort_noalloc.argtypes = [P, P, P, P, U32, I64, I64, P, P, I64, I64, I64, U32, P, P]
     lib.tile_sort_noalloc.restype = S
-    lib.tile_permute.argtypes = [P, P, U32, I64, I64, P, U32, P, P, I64, I64, U32, P, SZ, P]
+    lib.tile_permute.argtypes = [P, P, U32, I64, I64, P, P, P, U32, P, P, I64, I64, U32, P, SZ, P]
     lib.ts_device_sort.argtypes = [P, P, P, P, P, I64, U32, P, SZ, P]
     lib.ts_device_partition.argtypes = [P, P, P, P, P, I64, U32, U32, P, SZ, P]
     for f in ("tile_sort", "tile_partition", "tile_permute", "ts_device_sort", "ts_device_partition"):

@@ -9,7 +9,9 @@ stay exact integers throughout.
   gather would route twice).
 * ``SortWithPayload``: keys are fp32, sorted ascending through the order-preserving
   bit map (stable; -0 before +0); payload_out[:, k] = payload[:, perm[k]] and
-  sorted_keys[k] = keys[perm[k]]; backward scatters: dp[:, perm[k]] = dpo[:, k].
+  sorted_keys[k] = keys[perm[k]]; backward scatters: dp[:, perm[k]] = dpo[:, k], and
+  the key gradient the same way, both by one routing per tile (the key gradient rides
+  as an extra channel of the payload gradient's scatter).
 """
 from __future__ import annotations
 
@@ -65,10 +67,16 @@ class SortWithPayload(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_keys, g_payload, g_perm):
         perm, offsets = ctx.saved_tensors
+        want_k = g_keys is not None and ctx.needs_input_grad[0]
+        want_p = g_payload is not None and ctx.needs_input_grad[1]
         gk = gp = None
-        if g_keys is not None and ctx.needs_input_grad[0]:
+        if want_k and want_p:
+            # one routing per tile moves both: the key gradient as the extra channel
+            gp, gk = ops.tile_permute(g_payload.contiguous(), perm, "scatter", offsets, ctx.max_tile_len,
+                                      aux=g_keys.contiguous())
+        elif want_k:
             gk = ops.tile_permute(g_keys.contiguous(), perm, "scatter", offsets, ctx.max_tile_len)
-        if g_payload is not None and ctx.needs_input_grad[1]:
+        elif want_p:
             gp = ops.tile_permute(g_payload.contiguous(), perm, "scatter", offsets, ctx.max_tile_len)
         return gk, gp, None, None
 

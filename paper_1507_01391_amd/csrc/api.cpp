@@ -151,7 +151,7 @@ size_t ts_workspace_bytes(int op, uint32_t flags, int64_t num_tiles, int64_t tot
     if (op != TS_OP_SORT || num_tiles <= 0 || total_len < 0) return kWorkspaceBytes;
     const int sched = resolve_sort_sched(flags, max_tile_len, num_tiles);
     if (sched == TS_SCHED_MERGE) return ts::merge_layout(num_tiles, total_len, max_tile_len).total;
-    // a payload without perm_out keeps the permutation in the workspace
+    // a payload moved in a second launch keeps the (inverse) permutation in the workspace
     if (channels > 0) return kWorkspaceBytes + (size_t)total_len * 4u;
     return kWorkspaceBytes;
 }
@@ -274,7 +274,8 @@ ts_status tile_partition(const uint32_t* labels_in, uint32_t* labels_out,
 }
 
 ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int64_t elem_stride,
-                       int64_t chan_stride, const int32_t* pi, uint32_t direction, int32_t* inv_out,
+                       int64_t chan_stride, const uint32_t* aux_in, uint32_t* aux_out, const int32_t* pi,
+                       uint32_t direction, int32_t* inv_out,
                        const int64_t* tile_offsets, int64_t num_tiles, int64_t max_tile_len,
                        uint32_t flags, void* workspace, size_t workspace_bytes, void* stream) {
     ts_status st = check_common(tile_offsets, num_tiles, max_tile_len, workspace, workspace_bytes);
@@ -282,7 +283,13 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int
     if (direction != TS_SCATTER && direction != TS_GATHER)
         return fail(TS_ERR_INVALID, "tile_permute: direction must be TS_SCATTER or TS_GATHER");
     if (num_tiles > 0 && pi == nullptr) return fail(TS_ERR_INVALID, "tile_permute: pi is NULL");
-    if (channels == 0 && inv_out == nullptr) return TS_OK;
+    if ((aux_in == nullptr) != (aux_out == nullptr))
+        return fail(TS_ERR_INVALID, "tile_permute: aux_in and aux_out must both be given");
+    if (aux_in != nullptr && (const void*)aux_in == (const void*)aux_out)
+        return fail(TS_ERR_INVALID, "tile_permute: aux_in and aux_out alias");
+    if (aux_in != nullptr && sched_of(flags) == TS_SCHED_NAIVE)
+        return fail(TS_ERR_UNSUPPORTED, "tile_permute: the naive schedule has no aux channel");
+    if (channels == 0 && aux_in == nullptr && inv_out == nullptr) return TS_OK;
     if (channels > 0) {
         if (in == nullptr || out == nullptr) return fail(TS_ERR_INVALID, "tile_permute: in/out is NULL");
         st = check_payload(in, out, channels, elem_stride, chan_stride, true);
@@ -299,6 +306,7 @@ ts_status tile_permute(const uint32_t* in, uint32_t* out, uint32_t channels, int
         return fail(TS_ERR_UNSUPPORTED, "tile_permute: max_tile_len x elem_stride too large");
     ts::PermuteArgs a{};
     a.pay = ts::PayloadRef{in, out, channels, elem_stride, chan_stride};
+    a.aux = ts::PayloadRef{aux_in, aux_out, aux_in != nullptr ? 1u : 0u, 1, 0};
     a.pi = pi;
     a.direction = direction;
     a.inv_out = inv_out;
@@ -363,33 +371,45 @@ ts_status tile_sort(const uint32_t* keys_in, uint32_t* keys_out, const uint32_t*
         return hip_status(ts::launch_sort_merge(a, total_len, max_tile_len, workspace, s),
                           "tile_sort launch");
     }
-    // The payload is moved by a gather through the permutation; without perm_out the
-    // permutation lives in the workspace after the 256-byte header.
-    if (channels > 0 && a.perm_out == nullptr) {
-        const size_t need = kWorkspaceBytes + (size_t)total_len * 4u;
-        if (workspace_bytes < need)
-            return fail(TS_ERR_WORKSPACE, "tile_sort: payload without perm_out needs %zu workspace bytes", need);
-        a.perm_out = (int32_t*)((char*)workspace + kWorkspaceBytes);
-    }
     // A small batch sorted by the split schedule gathers the payload in the sort
     // kernel's store (a global gather inside each tile), sparing the second launch.
     a.fuse_pay = (channels > 0 && sched == TS_SCHED_SPLIT && num_tiles <= g_sort_small_batch) ? 1u : 0u;
+    // Otherwise the payload follows in a second launch.  The conflict-free schedules
+    // write the inverse permutation (the rank of every source position) into the
+    // workspace after its 256-byte header, and the payload is scattered by it: one
+    // routing per tile, where a gather by the permutation needs two.  The baseline
+    // gathers by the permutation (kept in the workspace when perm_out is NULL).
+    const bool second = channels > 0 && !a.fuse_pay;
+    if (second) {
+        const size_t need = kWorkspaceBytes + (size_t)total_len * 4u;
+        if (workspace_bytes < need)
+            return fail(TS_ERR_WORKSPACE, "tile_sort: a payload needs %zu workspace bytes", need);
+        int32_t* scratch = (int32_t*)((char*)workspace + kWorkspaceBytes);
+        if (sched == TS_SCHED_NAIVE) {
+            if (a.perm_out == nullptr) a.perm_out = scratch;
+        } else {
+            a.inv_out = scratch;
+        }
+    }
     hipError_t e = (sched == TS_SCHED_NAIVE) ? ts::launch_sort_naive(a, max_tile_len, s)
                                              : ts::launch_sort(a, max_tile_len, sched, s);
     if (e != hipSuccess) return hip_status(e, "tile_sort launch");
-    if (channels > 0 && !a.fuse_pay) {
-        // the payload is not part of the composite: gather it by the permutation
-        // (a conflict-free routing per tile), or by a direct LDS gather for the baseline
+    if (second) {
         ts::PermuteArgs p{};
         p.pay = a.pay;
-        p.pi = a.perm_out;
-        p.direction = TS_GATHER;
         p.offsets = tile_offsets;
         p.num_tiles = num_tiles;
         p.err = a.err;
-        e = (sched == TS_SCHED_NAIVE) ? ts::launch_permute_naive(p, max_tile_len, s)
-                                      : ts::launch_permute_split(p, max_tile_len < 4096 ? 4096 : max_tile_len, s);
-        if (e != hipSuccess) return hip_status(e, "tile_sort payload gather launch");
+        if (sched == TS_SCHED_NAIVE) {
+            p.pi = a.perm_out;
+            p.direction = TS_GATHER;
+            e = ts::launch_permute_naive(p, max_tile_len, s);
+        } else {
+            p.pi = a.inv_out;
+            p.direction = TS_SCATTER;
+            e = ts::launch_permute_split(p, max_tile_len < 4096 ? 4096 : max_tile_len, s);
+        }
+        if (e != hipSuccess) return hip_status(e, "tile_sort payload launch");
     }
     return TS_OK;
 }

@@ -38,6 +38,7 @@ struct PartitionArgs {
 
 struct PermuteArgs {
     PayloadRef pay;     // in / out with channels and strides
+    PayloadRef aux;     // optional extra channel (unit stride) moved first by the same routing
     const int32_t* pi;
     uint32_t direction;
     int32_t* inv_out;   // optional: receives pi^-1 (inv_out[pi[i]] = i)
@@ -59,6 +60,7 @@ struct SortArgs {
     uint32_t f32;       // nonzero: keys are binary32 patterns
     uint32_t* err;
     uint32_t fuse_pay;  // split schedule: gather the payload in the sort kernel's store
+    int32_t* inv_out;   // optional: inverse permutation, inv_out[o + source] = rank
 };
 
 // One pass of the device-wide radix sort (device_sort.hip): tiles of 4096 items split

@@ -21,8 +21,9 @@ namespace ts {
 
 namespace {
 
-// REPLAY (for two or more payload channels): channel 0 is routed and recorded, the
-// other channels replay the record two per 64-bit item.
+// REPLAY (for two or more channels): the first channel is routed and recorded, the
+// other channels replay the record two per 64-bit item.  The channels are the optional
+// aux channel (first) and the payload channels.
 //
 // Global accesses go through buffer resources over the tile (pi, inv_out, and each
 // payload channel when its elements are contiguous): lanes past the end of the tile
@@ -39,8 +40,9 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
     const int lane0 = lane_id();
     const int w0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     constexpr bool gather = GATHER;
-    const bool with_pay = a.pay.channels > 0;
-    const bool unit = a.pay.es == 1;  // channel words contiguous: buffer accesses
+    const uint32_t has_aux = a.aux.in != nullptr ? 1u : 0u;
+    const uint32_t nch = a.pay.channels + has_aux;  // channels to move
+    const bool with_pay = nch > 0;
 
     for (int64_t t = blockIdx.x; t < a.num_tiles; t += gridDim.x) {
         // lane- and wave-derived values are recomputed per tile instead of being hoisted
@@ -63,25 +65,32 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
                                   : buffer_rsrc(a.pi + o, nb * 4u);
         // resources of the outputs are built where they are used (from opaque copies of
         // the tile offset), not kept in scalar registers across the routing
-        // payload channel c: words (o + g) * es + c * cs; a buffer over the tile's
-        // n * es words (the host keeps that below 2^32 bytes)
-        const uint32_t es = (uint32_t)a.pay.es;
-        auto pay_rsrc = [&](const uint32_t* base, uint32_t c) {
-            return buffer_rsrc(base + (int64_t)c * a.pay.cs + opaque_s64(o) * (int64_t)es, nb * es * 4u);
+        // channel c (the aux channel first, when there is one, then the payload
+        // channels): words (o + g) * es + c' * cs; a buffer over the tile's n * es words
+        // (the host keeps that below 2^32 bytes).  The aux channel has unit stride.
+        auto chan_es = [&](uint32_t c) { return (has_aux && c == 0) ? 1u : (uint32_t)a.pay.es; };
+        auto pay_rsrc = [&](bool out, uint32_t c) {
+            const int64_t oo = opaque_s64(o);
+            if (has_aux && c == 0) return buffer_rsrc((out ? a.aux.out : a.aux.in) + oo, nb * 4u);
+            const uint32_t* base = out ? a.pay.out : a.pay.in;
+            const uint32_t es = (uint32_t)a.pay.es;
+            return buffer_rsrc(base + (int64_t)(c - has_aux) * a.pay.cs + oo * (int64_t)es, nb * es * 4u);
         };
         // lane offsets are passed in from an opaque copy of the lane taken where the
         // access happens, so the compiler neither keeps per-column offsets live across a
         // routing nor shares them with values computed before it
         auto load_pay = [&](uint32_t c, uint32_t lane_off, uint32_t (&xv)[CPW]) {
-            const rsrc_t r = pay_rsrc(a.pay.in, c);
-            if (unit) buffer_load_columns<CPW, NT>(r, lane_off, xv);
+            const rsrc_t r = pay_rsrc(false, c);
+            const uint32_t es = chan_es(c);
+            if (es == 1) buffer_load_columns<CPW, NT>(r, lane_off, xv);
             else buffer_load_columns_strided<CPW, NT>(r, lane_off * es, 256u * es, xv);
         };
         // stores of whole columns, one uniform branch per call: lo32 (hi = false) or
-        // hi32 (hi = true) of x[j] to payload channel c; index values v[j] to inv_out
+        // hi32 (hi = true) of x[j] to channel c; index values v[j] to inv_out
         auto store_pay = [&](uint32_t c, uint32_t lane_off, const uint64_t (&x)[CPW], bool hi) {
-            const rsrc_t r = pay_rsrc(a.pay.out, c);
-            if (unit) {
+            const rsrc_t r = pay_rsrc(true, c);
+            const uint32_t es = chan_es(c);
+            if (es == 1) {
 #pragma unroll
                 for (int j = 0; j < CPW; ++j) buffer_store<NT>(r, lane_off + 256u * j, hi ? hi32(x[j]) : lo32(x[j]));
             } else {
@@ -157,8 +166,7 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
 
         // a scatter asked only for the inverse still routes once (with no payload);
         // with REPLAY only channel 0 is routed here
-        const uint32_t nroute = REPLAY ? 1u
-                                       : ((!gather && a.inv_out && a.pay.channels == 0) ? 1u : a.pay.channels);
+        const uint32_t nroute = REPLAY ? 1u : ((!gather && a.inv_out && nch == 0) ? 1u : nch);
         uint32_t pdst[REPLAY ? CPW : 1];
 #pragma unroll 1
         for (uint32_t c = 0; c < nroute; ++c) {
@@ -191,9 +199,9 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
         }
         if constexpr (REPLAY) {
 #pragma unroll 1
-            for (uint32_t c = 1; c < a.pay.channels; c += 2) {
+            for (uint32_t c = 1; c < nch; c += 2) {
                 const int lc = (int)opaque((uint32_t)lane);
-                const bool two = c + 1 < a.pay.channels;
+                const bool two = c + 1 < nch;
                 uint32_t x0[CPW], x1[CPW];
                 load_pay(c, lane_off_at(lc), x0);
                 load_pay(two ? c + 1 : c, lane_off_at(lc), x1);
@@ -214,7 +222,7 @@ void permute_split_kernel(PermuteArgs a, const int64_t* __restrict__ offs) {
 // loads and stores (every word is read or written once).
 template <int NW, int CAP, int WPE = 0, bool ONESHOT = false, bool NT = false>
 hipError_t launch_perm(const PermuteArgs& a, hipStream_t s) {
-    const bool replay = a.pay.channels >= 2;
+    const bool replay = a.pay.channels + (a.aux.in != nullptr ? 1u : 0u) >= 2;
     auto kern = (a.direction == 1)
                     ? (replay ? permute_split_kernel<NW, CAP, true, WPE, true, NT>
                               : permute_split_kernel<NW, CAP, true, WPE, false, NT>)

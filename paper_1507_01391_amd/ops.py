@@ -140,11 +140,14 @@ def tile_partition(labels: torch.Tensor, payload: Optional[torch.Tensor] = None,
 def tile_permute(x: Optional[torch.Tensor], pi: torch.Tensor, direction: str = "scatter",
                  offsets=None, max_tile_len: Optional[int] = None, schedule: str = "auto",
                  validate: bool = False, out: Optional[torch.Tensor] = None,
-                 inv_out: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
+                 inv_out: Optional[torch.Tensor] = None, aux: Optional[torch.Tensor] = None,
+                 aux_out: Optional[torch.Tensor] = None):
     """Apply tile-local permutations: scatter out[pi[i]] = x[i], gather out[i] = x[pi[i]].
     ``x`` is [N] or [C, N] (channel-planar), or None when only ``inv_out`` (receives
     inv_out[pi[i]] = i from the same routing) is wanted.  ``pi`` and ``inv_out`` are
-    int32, or int16 holding the 16-bit tile-local indices.  Returns ``out``."""
+    int32, or int16 holding the 16-bit tile-local indices.  ``aux`` is an optional extra
+    [N] 32-bit tensor moved by the same routing (into ``aux_out``).  Returns ``out``, or
+    (``out``, ``aux_out``) when ``aux`` is given."""
     assert pi.dtype in (torch.int32, torch.int16) and pi.is_cuda and pi.is_contiguous()
     n = pi.shape[0]
     dev = pi.device
@@ -155,6 +158,11 @@ def tile_permute(x: Optional[torch.Tensor], pi: torch.Tensor, direction: str = "
             out = torch.empty_like(x)
     if inv_out is not None:
         assert inv_out.dtype in (torch.int32, torch.int16) and inv_out.shape[0] == n and inv_out.is_contiguous()
+    if aux is not None:
+        aux = _as_words(aux, "aux")
+        assert aux.dim() == 1 and aux.shape[0] == n
+        if aux_out is None:
+            aux_out = torch.empty_like(aux)
     off = _offsets(offsets, n, dev)
     ch, es, cs = _payload_layout(x, n)
     d = {"scatter": _lib.TS_SCATTER, "gather": _lib.TS_GATHER}[direction]
@@ -165,10 +173,10 @@ def tile_permute(x: Optional[torch.Tensor], pi: torch.Tensor, direction: str = "
     if inv_out is not None and inv_out.dtype == torch.int16:
         flags |= _lib.TS_FLAG_INV_U16
     lib = _lib.load()
-    _lib.check(lib.tile_permute(_ptr(x), _ptr(out), ch, es, cs, _ptr(pi), d, _ptr(inv_out),
-                                _ptr(off), off.numel() - 1, _max_len(off, max_tile_len), flags,
-                                _ptr(ws), ws.numel() * 4, _stream(dev)))
-    return out
+    _lib.check(lib.tile_permute(_ptr(x), _ptr(out), ch, es, cs, _ptr(aux), _ptr(aux_out), _ptr(pi), d,
+                                _ptr(inv_out), _ptr(off), off.numel() - 1, _max_len(off, max_tile_len),
+                                flags, _ptr(ws), ws.numel() * 4, _stream(dev)))
+    return out if aux is None else (out, aux_out)
 
 
 def tile_sort(keys: torch.Tensor, payload: Optional[torch.Tensor] = None, offsets=None,

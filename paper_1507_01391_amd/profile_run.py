@@ -8,6 +8,8 @@ in a fixed order, so counter rows map to patterns by dispatch order (PROBE_PATTE
     python -m paper_1507_01391_amd.profile_run partition --schedule split --tiles 16384
     python -m paper_1507_01391_amd.profile_run permute --schedule split --direction gather
     python -m paper_1507_01391_amd.profile_run permute --n 16384 --tiles 1024 --channels 8
+    python -m paper_1507_01391_amd.profile_run permute_fwd_bwd --tiles 16384
+    python -m paper_1507_01391_amd.profile_run sort_payload --rows 4096
     python -m paper_1507_01391_amd.profile_run sort --schedule bitonic --tiles 16384
     python -m paper_1507_01391_amd.profile_run segments --segments 20000
     python -m paper_1507_01391_amd.profile_run device_sort --n 268435456 --payload
@@ -96,6 +98,38 @@ def run_permute(a):
                                      schedule=a.schedule), a.reps)
 
 
+def run_permute_fwd_bwd(a):
+    """Forward scatter writing a 16-bit inverse, backward scatter by it: the path of
+    autograd.Permute (and of the fwd+bwd permutation workload of bench.py)."""
+    x, pi, g, off = inputs.permutation(num_tiles=a.tiles, n=a.n, family=a.family)
+    dx, dpi, dg, do = _dev(x), _dev(pi), _dev(g), _dev(off)
+    y, gx = torch.empty_like(dx), torch.empty_like(dx)
+    inv = torch.empty(dpi.shape, dtype=torch.int16, device=dpi.device)
+
+    def step():
+        ops.tile_permute(dx, dpi, "scatter", do, max_tile_len=a.n, out=y, inv_out=inv)
+        ops.tile_permute(dg, inv, "scatter", do, max_tile_len=a.n, out=gx)
+    _repeat(step, a.reps)
+
+
+def run_sort_payload(a):
+    """Differentiable sort of rows of fp32 keys with an 8-channel planar payload, forward
+    and backward (the path of bench.py's sort-with-payload workload)."""
+    from .autograd import sort_with_payload
+    keys, payload, grad, off = inputs.sort_payload(rows=a.rows, n=a.n)
+    dk = _dev(keys).view(torch.float32).requires_grad_(True)
+    dp = _dev(payload).view(torch.float32).requires_grad_(True)
+    dg, do = _dev(grad).view(torch.float32), _dev(off)
+    gk = torch.ones_like(dk)
+
+    def step():
+        sk, sp, _ = sort_with_payload(dk, dp, do, a.n)
+        torch.autograd.backward([sk, sp], [gk, dg])
+        dk.grad = None
+        dp.grad = None
+    _repeat(step, a.reps)
+
+
 def run_sort(a):
     rng = np.random.default_rng(inputs.SEED_BASE + 1)
     keys = rng.integers(0, 2**32, size=a.tiles * a.n, dtype=np.uint32)
@@ -151,6 +185,13 @@ def main(argv=None):
     p.add_argument("--tiles", type=int, default=4096)
     p.add_argument("--n", type=int, default=8192)
     p.add_argument("--channels", type=int, default=1)
+    p = sub.add_parser("permute_fwd_bwd")
+    p.add_argument("--family", default="uniform")
+    p.add_argument("--tiles", type=int, default=16384)
+    p.add_argument("--n", type=int, default=8192)
+    p = sub.add_parser("sort_payload")
+    p.add_argument("--rows", type=int, default=4096)
+    p.add_argument("--n", type=int, default=16384)
     p = sub.add_parser("sort")
     p.add_argument("--schedule", default="bitonic")
     p.add_argument("--tiles", type=int, default=16384)
@@ -168,7 +209,8 @@ def main(argv=None):
     for sp in sub.choices.values():
         sp.add_argument("--reps", type=int, default=2)
     a = ap.parse_args(argv)
-    {"partition": run_partition, "permute": run_permute, "sort": run_sort,
+    {"partition": run_partition, "permute": run_permute, "permute_fwd_bwd": run_permute_fwd_bwd,
+     "sort_payload": run_sort_payload, "sort": run_sort,
      "segments": run_segments, "device_sort": run_device_sort, "copy": run_copy, "probe": run_probe}[a.cmd](a)
     print(f"done {a.cmd}", file=sys.stderr, flush=True)
 

@@ -142,17 +142,26 @@ def test_permute_argument_validation(lib):
     P = ctypes.c_void_p
     fake, ws, pi = P(0x1000), P(0x2000), P(0x4000)
     # inverse output aliasing pi
-    rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, pi, 0, pi, fake, 1, 4096, 0, ws, 256, None)
+    rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, None, None, pi, 0, pi, fake, 1, 4096, 0, ws, 256, None)
     assert rc == 1 and "inv_out" in _err(lib)
     # bad direction
-    rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, pi, 5, None, fake, 1, 4096, 0, ws, 256, None)
+    rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, None, None, pi, 5, None, fake, 1, 4096, 0, ws, 256, None)
     assert rc == 1 and "direction" in _err(lib)
     # no payload and no inverse wanted: nothing to do
-    rc = lib.tile_permute(None, None, 0, 1, 0, pi, 0, None, fake, 1, 4096, 0, ws, 256, None)
+    rc = lib.tile_permute(None, None, 0, 1, 0, None, None, pi, 0, None, fake, 1, 4096, 0, ws, 256, None)
     assert rc == 0
     # tiles longer than the routing capacity
-    rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, pi, 0, None, fake, 1, 32768, 0, ws, 256, None)
+    rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, None, None, pi, 0, None, fake, 1, 32768, 0, ws, 256, None)
     assert rc == 2
+    # the aux channel: both pointers or neither, not aliased, not with the naive schedule
+    rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, P(0x5000), None, pi, 0, None, fake, 1, 4096, 0, ws, 256, None)
+    assert rc == 1 and "aux" in _err(lib)
+    rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, P(0x5000), P(0x5000), pi, 0, None, fake, 1, 4096, 0, ws, 256,
+                          None)
+    assert rc == 1 and "alias" in _err(lib)
+    rc = lib.tile_permute(fake, P(0x3000), 1, 1, 0, P(0x5000), P(0x6000), pi, 0, None, fake, 1, 4096, 15 << 8, ws,
+                          256, None)
+    assert rc == 2 and "aux" in _err(lib)
 
 
 def test_device_sort_argument_validation(lib):

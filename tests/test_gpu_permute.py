@@ -210,3 +210,29 @@ def test_64bit_payload(ts, oracle, direction, cap):
     d = oracle.SCATTER if direction == "scatter" else oracle.GATHER
     want = oracle.tile_permute(words, pi, d, off, nthreads=8)
     assert np.array_equal(got.cpu().numpy().view(np.uint32).reshape(n, 2).T, want)
+
+
+@pytest.mark.parametrize("direction", ["scatter", "gather"])
+@pytest.mark.parametrize("channels", [0, 1, 2, 8])
+@pytest.mark.parametrize("cap", [4096, 16384])
+def test_aux_channel(ts, oracle, direction, channels, cap):
+    """An extra unit-stride channel moved by the same routing as 0, 1, 2 or 8 planar
+    payload channels (routed first, the payload channels replayed), ragged tiles."""
+    from tests.gpu_util import dev, host_u32
+    rng = np.random.default_rng(cap + channels + (direction == "gather"))
+    sizes = np.concatenate([[cap, 0, 1, 65, cap - 1], rng.integers(0, cap + 1, size=6)])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    pi = np.concatenate([rng.permutation(int(s)) for s in sizes]).astype(np.int32)
+    aux = rng.integers(0, 2**32, size=n, dtype=np.uint32)
+    x = rng.integers(0, 2**32, size=(channels, n), dtype=np.uint32) if channels else None
+    d = oracle.SCATTER if direction == "scatter" else oracle.GATHER
+    if channels == 0:
+        got_aux = ts.tile_permute(None, dev(pi), direction, dev(off), max_tile_len=cap, aux=dev(aux))[1]
+    else:
+        got, got_aux = ts.tile_permute(dev(x[0] if channels == 1 else x), dev(pi), direction, dev(off),
+                                       max_tile_len=cap, aux=dev(aux))
+        want = oracle.tile_permute(x, pi, d, off, nthreads=8)
+        assert np.array_equal(host_u32(got).reshape(want.shape), want)
+    ts.check_device_errors()
+    assert np.array_equal(host_u32(got_aux), oracle.tile_permute(aux, pi, d, off, nthreads=8))
