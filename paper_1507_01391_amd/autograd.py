@@ -62,6 +62,9 @@ class SortWithPayload(torch.autograd.Function):
         ctx.save_for_backward(perm, offsets)
         ctx.max_tile_len = max_tile_len
         ctx.mark_non_differentiable(perm)
+        # gradients of outputs that the loss does not use arrive as None instead of
+        # being materialised as zero tensors (the permutation's would be a 4 B/key fill)
+        ctx.set_materialize_grads(False)
         return k, p, perm
 
     @staticmethod

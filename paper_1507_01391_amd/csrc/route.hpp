@@ -2,29 +2,33 @@
 //
 // This is the permutation problem of Afshani & Sitchinava (Sec. 1, "Problems of
 // interest": an item labelled (i, j) goes to slot j of bank i), solved by
-// reducing it to a balanced w-way partition by destination bank followed by an
-// in-bank placement:
+// reducing it to a balanced partition by destination bank class followed by an
+// in-bank placement.  Items are 64 bits, so a slot s occupies the bank pair
+// 2s mod 64 and two slots share banks iff they are congruent modulo 32: the class of a
+// destination is dst mod 32.
 //
-//  1. Six binary splits, most significant bank bit first.  At level L the tile is
-//     2^L equal segments; every segment sends the items whose next bank bit is 0
+//  1. Five binary splits, most significant class bit first.  At level L the tile is
+//     2^L equal segments; every segment sends the items whose next class bit is 0
 //     forward from its front and those whose bit is 1 backward from its back.
 //     Because the destinations form a permutation, each half receives exactly
 //     half the items, so segment boundaries stay at fixed multiples of the
 //     column size, and every column's 64 writes land on 64 cyclically
-//     consecutive slots: one per bank, for any phase grouping (the same
-//     argument as the partition kernel's split).  Reads are linear.
-//  2. After the splits, group g (m = N/64 consecutive slots) holds exactly the m
-//     items bound for bank g.  In placement step t lane l reads item
-//     (t + l) mod m of group l (a skewed, conflict-free read) and writes it to
-//     its destination slot, which lies in bank l: every lane writes its own bank.
+//     consecutive slots: distinct banks for any phase grouping (the same argument
+//     as the partition kernel's split).  Reads are linear.
+//  2. After the splits, group g (2m = N/32 consecutive slots) holds exactly the 2m
+//     items bound for class g.  In placement step t lane l reads item
+//     (t + (l mod 32) + m (l / 32)) mod 2m of group l mod 32 (lanes l and l + 32 take
+//     the two halves of the group; every 32-lane phase of the read meets 32 distinct
+//     slot residues) and writes it to its destination slot, of class l mod 32: the 16
+//     lanes of a 64-bit write phase reach 16 distinct classes.
 //
-// The high word of an item is its key: the destination bank (dst mod 64) in bits
-// 31..26, the slot inside the bank (dst / 64) in bits 25..18 and a 14-bit source index
-// in bits 13..0.  With the bank bits on top, all items of a level-L segment share the
-// key's top L bits (the segment index), so the bank bit split at that level is one
-// unsigned comparison against a per-segment threshold.  The tile is padded to the
-// capacity; padding items must carry the unused destinations so that every bank still
-// receives exactly N/64 items.
+// The high word of an item is its key: the destination class (dst mod 32) in bits
+// 31..27, dst / 32 in bits 26..18 and a 14-bit source index in bits 13..0.  With the
+// class bits on top, all items of a level-L segment share the key's top L bits (the
+// segment index), so the class bit split at that level is one unsigned comparison
+// against a per-segment threshold.  The tile is padded to the capacity; padding items
+// must carry the unused destinations so that every class still receives exactly N/32
+// items.
 //
 // A routing can be recorded (every column's ballot at every level, the zeros before
 // each wave at the levels whose segments span waves, and every item's placement slot)
@@ -37,18 +41,21 @@
 
 namespace ts {
 
+// Split levels of a routing: 32 destination classes.
+constexpr int ROUTE_LEVELS = 5;
+
 // Key of an item bound for slot dst (< 16384) with source index src (< 16384).
 TS_DEV uint32_t route_key(uint32_t dst, uint32_t src) {
-    return ((dst & 63u) << 26) | ((dst >> 6) << 18) | src;
+    return ((dst & 31u) << 27) | ((dst >> 5) << 18) | src;
 }
-TS_DEV uint32_t key_dst(uint32_t key) { return (((key >> 18) & 0xFFu) << 6) | (key >> 26); }
+TS_DEV uint32_t key_dst(uint32_t key) { return (((key >> 18) & 0x1FFu) << 5) | (key >> 27); }
 TS_DEV uint32_t key_src(uint32_t key) { return key & 0x3FFFu; }
 
 template <int NW, int CAP>
 struct Router {
     static constexpr int NCOL = CAP / 64;   // columns of the tile
     static constexpr int CPW = NCOL / NW;   // columns per wave
-    static constexpr int M = CAP / 64;      // items per bank
+    static constexpr int M = CAP / 64;      // half the items of a class
     static constexpr int LOG_NCOL = __builtin_ctz(NCOL);
     static_assert(CPW * NW == NCOL, "capacity must split evenly over the waves");
     static_assert(M >= 64, "tiles of at least 64 x 64 items");
@@ -57,11 +64,11 @@ struct Router {
 
     // Record of one routing (lives in LDS next to A).
     struct Plan {
-        uint64_t bal[6][NCOL];   // ballot of every column at every level
-        int zb[6][NW];           // zeros of the segment before each wave's first column
+        uint64_t bal[ROUTE_LEVELS][NCOL];   // ballot of every column at every level
+        int zb[ROUTE_LEVELS][NW];           // zeros of the segment before each wave's first column
     };
 
-    // One binary split (level L, bank bit 5 - L) of every segment.  MODE 0: route;
+    // One binary split (level L, class bit 4 - L) of every segment.  MODE 0: route;
     // 1: route and record into *plan; 2: replay the split recorded in *plan.
     //
     // Column k (k_in = k mod segment columns) writes a zero to seg_base + z + r0 and a one
@@ -142,19 +149,22 @@ struct Router {
         split_level<2, MODE>(A, wz, e, w, lane, plan);
         split_level<3, MODE>(A, wz, e, w, lane, plan);
         split_level<4, MODE>(A, wz, e, w, lane, plan);
-        split_level<5, MODE>(A, wz, e, w, lane, plan);
+        static_assert(ROUTE_LEVELS == 5, "five class bits");
     }
 
-    // Placement: group g = slots [g*M, (g+1)*M) holds the items for bank g.  Wave w
-    // performs steps t = w*CPW + j; lane l reads item (t + l) mod M of group l and then
-    // writes it to its destination (bank l).
+    // Placement: group g = slots [2Mg, 2M(g+1)) holds the items for class g.  Wave w
+    // performs steps t = w*CPW + j; lane l reads item (t + (l mod 32) + M (l / 32)) mod 2M
+    // of group l mod 32 and then writes it to its destination (class l mod 32).
     static TS_DEV void gather_groups(const uint64_t* A, uint64_t (&e)[CPW], int w, int lane) {
         __syncthreads();  // every wave's groups are complete
         const int lane_o = (int)opaque((uint32_t)lane);
+        const uint32_t g = (uint32_t)lane_o & 31u;
+        const uint32_t base = g * (2 * M);
+        const uint32_t rot = g + (((uint32_t)lane_o >> 5) * M);
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
             const int t = w * CPW + j;
-            const uint32_t slot = (uint32_t)lane_o * M + (uint32_t)((t + lane_o) & (M - 1));
+            const uint32_t slot = base + (((uint32_t)t + rot) & (uint32_t)(2 * M - 1));
             e[j] = lds_load(A, slot * 8u);
         }
         __syncthreads();  // all groups read before any slot is overwritten
