@@ -31,6 +31,9 @@ PERMUTE_BYTES_PER_ELEM = 12
 # LDS bytes per key of the partition kernel: six binary splits, each writing and reading
 # every 8-byte item once.
 PARTITION_LDS_BYTES_PER_KEY = 6 * 2 * 8
+# LDS bytes per element of the fwd+bwd permutation: two routings, each five class
+# splits and the placement writing and reading every 8-byte item once.
+PERMUTE_LDS_BYTES_PER_ELEM = 2 * 6 * 2 * 8
 # Uneven segmented sort: keys in and out, payload word in and out.
 SEGMENTS_BYTES_PER_KEY = 16
 # Differentiable sort-with-payload, 8 channels, per key: forward keys in + sorted keys
@@ -58,7 +61,9 @@ MEASURED = {
            "sha256_prefix": None, "knobs": {"partition_waves_4096": 168}},
     "c3": {"profile": "profiles/permute_c3_counters.md",
            "sources": [KSRC + "permute.hip", KSRC + "route.hpp", KSRC + "common.hpp"],
-           "sha256_prefix": None, "knobs": {}},
+           "sha256_prefix": "dc6fac464e9cf033", "knobs": {"permute_variant": 6},
+           "fetch": 919719 * 2 * 1024, "write": 1310728 * 1024,
+           "lds_insts": 44040192, "lds_active": 201326592, "lds_conflicts": 0},
     "c4": {"profile": "profiles/merge_c4_counters.md",
            "sources": [KSRC + "merge.hip", KSRC + "bitonic.hpp", KSRC + "common.hpp"],
            "sha256_prefix": "24a8ade22f7f8218", "knobs": {"merge_wide": 32768},
@@ -369,7 +374,7 @@ def bench_c3(args, torch, ts, inputs, orc):
     out = {"metric": "fwd+bwd permute GB/s (24 B per element)", "value": variants_out["split"],
            "unit": "GB/s", "workload": f"{T} tiles x 8192 fp32, uniform random pi per tile",
            "roofline": roofline(2 * PERMUTE_BYTES_PER_ELEM, n, means["split"],
-                                measured("c3", ts) if T == 16384 else None),
+                                measured("c3", ts) if T == 16384 else None, PERMUTE_LDS_BYTES_PER_ELEM),
            "variants_GBps": variants_out,
            "naive_best_GBps": max(variants_out["naive"], variants_out["naive_oneshot"]),
            "parity_sampled_tiles": "8 tiles bit-exact" if ok else "MISMATCH"}

@@ -28,10 +28,11 @@ PLAN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "plans")
 # knob -> (candidate values, default)
 SORT = {"split": 1, "thm2": 2, "bitonic": 3, "merge": 4, "naive": 15}
 KNOBS = {
-    "sort_plan_4096": ([SORT["bitonic"], SORT["merge"], SORT["split"]], SORT["bitonic"]),
-    "sort_plan_8192": ([SORT["merge"], SORT["split"]], SORT["merge"]),
-    "sort_plan_16384": ([SORT["merge"], SORT["split"]], SORT["merge"]),
+    "sort_plan_4096": ([SORT["bitonic"], SORT["merge"], SORT["split"], SORT["thm2"]], SORT["bitonic"]),
+    "sort_plan_8192": ([SORT["merge"], SORT["split"], SORT["bitonic"], SORT["thm2"]], SORT["merge"]),
+    "sort_plan_16384": ([SORT["merge"], SORT["split"], SORT["bitonic"], SORT["thm2"]], SORT["merge"]),
     "merge_pack": ([1, 0], 1),
+    "merge_wide": ([32768, 16384, 8192, 4096], 32768),
     "oneshot": ([1, 0], 1),
     "partition_waves_4096": ([168, 176, 166, 164, 106, 108, 104], 168),
     "permute_variant": ([6, 7, 8, 9, 1, 0, 2], 6),
@@ -146,6 +147,10 @@ def tune(quick: bool = False, log=print) -> dict:
     # as in the uneven-segment workload
     run, n = _sort_bench(rng, 256, 4096, total, lambda v: "merge", log_uniform=True, payload=True)
     choose("merge_pack", run, n, set_knob=True)
+    # longest tile the merge schedule sorts whole in one workgroup: the full range of
+    # the uneven-segment workload
+    run, n = _sort_bench(rng, 256, 32768, total, lambda v: "merge", log_uniform=True, payload=True)
+    choose("merge_wide", run, n, set_knob=True)
 
     # launch shape of the kernels without a variant table: a partition of 2048-item
     # tiles plus a permutation of 4096-item tiles

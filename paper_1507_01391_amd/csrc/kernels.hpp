@@ -60,7 +60,6 @@ struct SortArgs {
     uint32_t f32;       // nonzero: keys are binary32 patterns
     uint32_t* err;
     uint32_t fuse_pay;  // split schedule: gather the payload in the sort kernel's store
-    int32_t* inv_out;   // optional: inverse permutation, inv_out[o + source] = rank
 };
 
 // One pass of the device-wide radix sort (device_sort.hip): tiles of 4096 items split

@@ -48,7 +48,6 @@ struct SplitArgs {
     int64_t pay_es;
     uint32_t has_pay;
     int32_t* perm_out;
-    int32_t* inv_out;           // MODE 1: inv_out[o + source] = rank (a scattered store)
     int64_t num_tiles;
     uint32_t num_classes;       // MODE 0: labels must be below this
     int nbits;                  // bits to split on
@@ -343,15 +342,6 @@ void split_kernel(SplitArgs a, const int64_t* __restrict__ offs) {
 #pragma unroll
                 for (int j = 0; j < CPW; ++j) buffer_store<NTS>(r, off + 256u * j, v[j]);
             }
-            if (MODE == 1 && a.inv_out != nullptr) {
-                // the inverse permutation: the rank of every source position (positions
-                // of real ranks are real items, inside the tile)
-#pragma unroll
-                for (int j = 0; j < CPW; ++j) {
-                    const int r = 64 * (w * CPW + j) + ls;
-                    if (r < n) a.inv_out[o + lo32(e[j])] = r;
-                }
-            }
             if (MODE != 2 && a.gpay.out != nullptr) {
                 // rank v takes the words of its source position; both stay inside the tile
                 // (MODE 0: the payload channels after the first, which rides in the item)
@@ -485,7 +475,6 @@ hipError_t launch_sort_split(const SortArgs& q, int64_t max_len, hipStream_t s) 
     a.keys_in = q.keys_in;
     a.keys_out = q.keys_out;
     a.perm_out = q.perm_out;
-    a.inv_out = q.inv_out;
     a.num_tiles = q.num_tiles;
     a.nbits = 32;
     a.f32 = q.f32;

@@ -170,7 +170,6 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
                 const uint32_t key = hi32(v[c]);
                 if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
                 if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)lo32(v[c]));
-                if (a.inv_out) a.inv_out[o + lo32(v[c])] = r;
             }
         }
         if (a.fuse_pay) {
@@ -364,7 +363,6 @@ void thm2_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
                 const uint32_t key = hi32(v[c]);
                 if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
                 if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)lo32(v[c]));
-                if (a.inv_out) a.inv_out[o + lo32(v[c])] = r;
             }
         }
         if (a.fuse_pay) {
@@ -434,7 +432,6 @@ void bitonic_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
                 const uint32_t key = hi32(v[c]);
                 if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
                 if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)lo32(v[c]));
-                if (a.inv_out) a.inv_out[o + lo32(v[c])] = r;
             }
         }
         if (a.fuse_pay) {

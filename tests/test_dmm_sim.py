@@ -276,3 +276,32 @@ def test_router_five_class_splits_group_by_class():
         # the key round-trips the destination and the source
         back = (((key >> 18) & 0x1FF) << 5) | (key >> 27)
         assert np.array_equal(back, dst) and np.array_equal(key & 0x3FFF, np.arange(n))
+
+
+@pytest.mark.parametrize("banks,phase,width", [(32, 32, 1), (64, 32, 2), (64, 16, 2), (64, 64, 1)])
+@pytest.mark.parametrize("is_read", [True, False])
+def test_batch_conflicts_match_step_conflicts(sim, banks, phase, width, is_read):
+    """The many-step count used for the counter predictions equals the one-step
+    simulator on random address patterns (with repeated words and small ranges)."""
+    from oracle import sim_predict
+    rng = np.random.default_rng(banks + phase + width + is_read)
+    model = sim.BankModel(banks, phase, width)
+    for hi in (64, 200, 8192):
+        words = rng.integers(0, hi, size=(40, 64)) * width
+        got = sim_predict.batch_conflicts(words, model, is_read=is_read)
+        want = [sim.step_conflicts(list(enumerate(w)), model, is_read=is_read) for w in words]
+        assert list(got) == want
+
+
+def test_naive_permute_prediction_closed_forms():
+    """The transpose and bit-reversal families put all 32 lanes of a half on one bank
+    (31 extra cycles per half, 62 per scattered instruction), the identity none."""
+    from oracle import sim_predict
+    n = 8192
+    i = np.arange(n)
+    transpose = (i % 64) * 128 + i // 64
+    bitrev = np.array([int(f"{v:013b}"[::-1], 2) for v in range(n)])
+    for pi in (transpose, bitrev):
+        r = sim_predict.naive_permute_conflicts(pi, n, "scatter")
+        assert r == {"instructions": 2 * n // 64, "conflict_cycles": 62 * n // 64}
+    assert sim_predict.naive_permute_conflicts(i, n, "gather")["conflict_cycles"] == 0
