@@ -31,9 +31,9 @@ PERMUTE_BYTES_PER_ELEM = 12
 # LDS bytes per key of the partition kernel: six binary splits, each writing and reading
 # every 8-byte item once.
 PARTITION_LDS_BYTES_PER_KEY = 6 * 2 * 8
-# LDS bytes per element of the fwd+bwd permutation: two routings, each five class
+# LDS bytes per element of the fwd+bwd permutation: two routings, each four class
 # splits and the placement writing and reading every 8-byte item once.
-PERMUTE_LDS_BYTES_PER_ELEM = 2 * 6 * 2 * 8
+PERMUTE_LDS_BYTES_PER_ELEM = 2 * 5 * 2 * 8
 # Uneven segmented sort: keys in and out, payload word in and out.
 SEGMENTS_BYTES_PER_KEY = 16
 # Differentiable sort-with-payload, 8 channels, per key: forward keys in + sorted keys
@@ -58,12 +58,14 @@ KSRC = "paper_1507_01391_amd/csrc/"
 MEASURED = {
     "c2": {"profile": "profiles/partition_split_c2_counters.md",
            "sources": [KSRC + "partition.hip", KSRC + "common.hpp"],
-           "sha256_prefix": None, "knobs": {"partition_waves_4096": 168}},
+           "sha256_prefix": "bdcad124808c3696", "knobs": {"partition_waves_4096": 168},
+           "fetch": 1052741 * 2 * 1024, "write": 2097168 * 1024,
+           "lds_insts": 56623104, "lds_active": 163577856, "lds_conflicts": 0},
     "c3": {"profile": "profiles/permute_c3_counters.md",
            "sources": [KSRC + "permute.hip", KSRC + "route.hpp", KSRC + "common.hpp"],
-           "sha256_prefix": "dc6fac464e9cf033", "knobs": {"permute_variant": 6},
-           "fetch": 919719 * 2 * 1024, "write": 1310728 * 1024,
-           "lds_insts": 44040192, "lds_active": 201326592, "lds_conflicts": 0},
+           "sha256_prefix": "c5064b065efa7f57", "knobs": {"permute_variant": 6},
+           "fetch": 919709 * 2 * 1024, "write": 1310737 * 1024,
+           "lds_insts": 37748736, "lds_active": 167772160, "lds_conflicts": 0},
     "c4": {"profile": "profiles/merge_c4_counters.md",
            "sources": [KSRC + "merge.hip", KSRC + "bitonic.hpp", KSRC + "common.hpp"],
            "sha256_prefix": "24a8ade22f7f8218", "knobs": {"merge_wide": 32768},
@@ -71,8 +73,10 @@ MEASURED = {
            "lds_insts": 582923358, "lds_active": 2533340340, "lds_conflicts": 0},
     "c5": {"profile": "profiles/sort_payload_c5_counters.md",
            "sources": [KSRC + "partition.hip", KSRC + "permute.hip", KSRC + "route.hpp", KSRC + "common.hpp",
-                       "paper_1507_01391_amd/autograd.py", "paper_1507_01391_amd/plans/gfx950.json"],
-           "sha256_prefix": None, "knobs": {}},
+                       KSRC + "api.cpp", "paper_1507_01391_amd/autograd.py"],
+           "sha256_prefix": "b64936f92f5089b3", "knobs": {"sort_plan_16384": 1, "oneshot": 1},
+           "fetch": 2670155 * 2 * 1024, "write": 5163518 * 1024,
+           "lds_insts": 192937984, "lds_active": 824180736, "lds_conflicts": 0},
 }
 
 

@@ -184,32 +184,42 @@ TS_DEV void bitonic_merge4096(uint32_t* A, uint64_t (&v)[R], int lane) {
 // Tiles spread over H wavefronts of one workgroup (H = 2, 4, 8): every wavefront holds
 // 4096 items in its 64 registers x 64 lanes.
 
+// Registers per exchange round of cross_wave_stage.
+constexpr int XCH = 32;
+
 // Compare-exchange of every register with the same register of wavefront hp (same
 // lane): the wavefront with the lower index keeps the smaller composite when `asc`.
-// Sixteen registers at a time go through LDS as 64-bit words, lane L of wavefront h at
-// slot (16 h + j) 64 + L of X (16 H x 64 slots): 16 (writes) or 32 (reads) consecutive
-// 8-byte slots per phase, no bank conflicts.  All H wavefronts take part (barriers).
+// XCH registers at a time go through LDS as 64-bit words, lane L of wavefront h at
+// slot (XCH h + j) 64 + L of X (XCH H x 64 slots): 16 (writes) or 32 (reads)
+// consecutive 8-byte slots per phase, no bank conflicts; two rounds of two barriers
+// each.  All H wavefronts take part.
 TS_DEV void cross_wave_stage(uint64_t* X, uint64_t (&v)[R], int h, int hp, bool asc, int lane) {
     const bool keep_min = (h < hp) == asc;
 #pragma unroll
-    for (int g = 0; g < R; g += 16) {
+    for (int g = 0; g < R; g += XCH) {
         __syncthreads();  // earlier readers of X are done
 #pragma unroll
-        for (int j = 0; j < 16; ++j) X[(16 * h + j) * 64 + lane] = v[g + j];
+        for (int j = 0; j < XCH; ++j) X[(XCH * h + j) * 64 + lane] = v[g + j];
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const uint64_t y = X[(16 * hp + j) * 64 + lane];
-            const uint64_t x = v[g + j];
-            v[g + j] = keep_min ? (y < x ? y : x) : (y < x ? x : y);
+        for (int j0 = 0; j0 < XCH; j0 += 16) {  // 16 partner registers in flight at a time
+#pragma unroll
+            for (int j = j0; j < j0 + 16; ++j) {
+                const uint64_t y = X[(XCH * hp + j) * 64 + lane];
+                const uint64_t x = v[g + j];
+                v[g + j] = keep_min ? (y < x ? y : x) : (y < x ? x : y);
+            }
         }
     }
 }
 
 // Words of LDS the wide bitonic sort needs: one transpose array per wavefront (the
-// exchange buffer of cross_wave_stage, 16 H x 64 x 2 words, fits in it).
+// exchange buffer of cross_wave_stage, XCH H x 64 x 2 words, fits in it).
 template <int H>
-constexpr int wide_bitonic_words() { return H * MOVE_WORDS; }
+constexpr int wide_bitonic_words() {
+    static_assert(XCH * H * 64 * 2 <= H * MOVE_WORDS, "the exchange buffer fits the transpose arrays");
+    return H * MOVE_WORDS;
+}
 
 // Batcher's bitonic sort of 4096 H composites held by H wavefronts (wavefront h = the
 // item indices 4096 h .. 4096 h + 4095).  Every wavefront sorts its own 4096 items

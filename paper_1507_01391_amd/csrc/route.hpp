@@ -4,10 +4,11 @@
 // interest": an item labelled (i, j) goes to slot j of bank i), solved by
 // reducing it to a balanced partition by destination bank class followed by an
 // in-bank placement.  Items are 64 bits, so a slot s occupies the bank pair
-// 2s mod 64 and two slots share banks iff they are congruent modulo 32: the class of a
-// destination is dst mod 32.
+// 2s mod 64, two slots share banks iff they are congruent modulo 32, and a 64-bit write
+// is served 16 lanes at a time: 16 lanes whose destinations are distinct modulo 16 are
+// also distinct modulo 32.  The class of a destination is dst mod 16.
 //
-//  1. Five binary splits, most significant class bit first.  At level L the tile is
+//  1. Four binary splits, most significant class bit first.  At level L the tile is
 //     2^L equal segments; every segment sends the items whose next class bit is 0
 //     forward from its front and those whose bit is 1 backward from its back.
 //     Because the destinations form a permutation, each half receives exactly
@@ -15,19 +16,19 @@
 //     column size, and every column's 64 writes land on 64 cyclically
 //     consecutive slots: distinct banks for any phase grouping (the same argument
 //     as the partition kernel's split).  Reads are linear.
-//  2. After the splits, group g (2m = N/32 consecutive slots) holds exactly the 2m
-//     items bound for class g.  In placement step t lane l reads item
-//     (t + (l mod 32) + m (l / 32)) mod 2m of group l mod 32 (lanes l and l + 32 take
-//     the two halves of the group; every 32-lane phase of the read meets 32 distinct
-//     slot residues) and writes it to its destination slot, of class l mod 32: the 16
-//     lanes of a 64-bit write phase reach 16 distinct classes.
+//  2. After the splits, group g (4m = N/16 consecutive slots) holds exactly the 4m
+//     items bound for class g.  Lane l = 16q + g (q = 0 .. 3) takes quarter q of group
+//     g: in placement step t it reads item q m + ((t + g + 16 q) mod m) of the group (the
+//     32 lanes of a read phase meet residues t + g and t + g + 16 modulo 32, all
+//     distinct) and writes it to its destination slot, of class g: the 16 lanes of a
+//     64-bit write phase reach 16 distinct classes.
 //
-// The high word of an item is its key: the destination class (dst mod 32) in bits
-// 31..27, dst / 32 in bits 26..18 and a 14-bit source index in bits 13..0.  With the
+// The high word of an item is its key: the destination class (dst mod 16) in bits
+// 31..28, dst / 16 in bits 27..18 and a 14-bit source index in bits 13..0.  With the
 // class bits on top, all items of a level-L segment share the key's top L bits (the
 // segment index), so the class bit split at that level is one unsigned comparison
 // against a per-segment threshold.  The tile is padded to the capacity; padding items
-// must carry the unused destinations so that every class still receives exactly N/32
+// must carry the unused destinations so that every class still receives exactly N/16
 // items.
 //
 // A routing can be recorded (every column's ballot at every level, the zeros before
@@ -41,21 +42,21 @@
 
 namespace ts {
 
-// Split levels of a routing: 32 destination classes.
-constexpr int ROUTE_LEVELS = 5;
+// Split levels of a routing: 16 destination classes.
+constexpr int ROUTE_LEVELS = 4;
 
 // Key of an item bound for slot dst (< 16384) with source index src (< 16384).
 TS_DEV uint32_t route_key(uint32_t dst, uint32_t src) {
-    return ((dst & 31u) << 27) | ((dst >> 5) << 18) | src;
+    return ((dst & 15u) << 28) | ((dst >> 4) << 18) | src;
 }
-TS_DEV uint32_t key_dst(uint32_t key) { return (((key >> 18) & 0x1FFu) << 5) | (key >> 27); }
+TS_DEV uint32_t key_dst(uint32_t key) { return (((key >> 18) & 0x3FFu) << 4) | (key >> 28); }
 TS_DEV uint32_t key_src(uint32_t key) { return key & 0x3FFFu; }
 
 template <int NW, int CAP>
 struct Router {
     static constexpr int NCOL = CAP / 64;   // columns of the tile
     static constexpr int CPW = NCOL / NW;   // columns per wave
-    static constexpr int M = CAP / 64;      // half the items of a class
+    static constexpr int M = CAP / 64;      // a quarter of the items of a class
     static constexpr int LOG_NCOL = __builtin_ctz(NCOL);
     static_assert(CPW * NW == NCOL, "capacity must split evenly over the waves");
     static_assert(M >= 64, "tiles of at least 64 x 64 items");
@@ -68,7 +69,7 @@ struct Router {
         int zb[ROUTE_LEVELS][NW];           // zeros of the segment before each wave's first column
     };
 
-    // One binary split (level L, class bit 4 - L) of every segment.  MODE 0: route;
+    // One binary split (level L, class bit 3 - L) of every segment.  MODE 0: route;
     // 1: route and record into *plan; 2: replay the split recorded in *plan.
     //
     // Column k (k_in = k mod segment columns) writes a zero to seg_base + z + r0 and a one
@@ -148,23 +149,22 @@ struct Router {
         split_level<1, MODE>(A, wz, e, w, lane, plan);
         split_level<2, MODE>(A, wz, e, w, lane, plan);
         split_level<3, MODE>(A, wz, e, w, lane, plan);
-        split_level<4, MODE>(A, wz, e, w, lane, plan);
-        static_assert(ROUTE_LEVELS == 5, "five class bits");
+        static_assert(ROUTE_LEVELS == 4, "four class bits");
     }
 
-    // Placement: group g = slots [2Mg, 2M(g+1)) holds the items for class g.  Wave w
-    // performs steps t = w*CPW + j; lane l reads item (t + (l mod 32) + M (l / 32)) mod 2M
-    // of group l mod 32 and then writes it to its destination (class l mod 32).
+    // Placement: group g = slots [4Mg, 4M(g+1)) holds the items for class g.  Wave w
+    // performs steps t = w*CPW + j; lane l = 16q + g reads item qM + ((t + g + 16q) mod M)
+    // of group g and then writes it to its destination (class g).
     static TS_DEV void gather_groups(const uint64_t* A, uint64_t (&e)[CPW], int w, int lane) {
         __syncthreads();  // every wave's groups are complete
         const int lane_o = (int)opaque((uint32_t)lane);
-        const uint32_t g = (uint32_t)lane_o & 31u;
-        const uint32_t base = g * (2 * M);
-        const uint32_t rot = g + (((uint32_t)lane_o >> 5) * M);
+        const uint32_t g = (uint32_t)lane_o & 15u, q = (uint32_t)lane_o >> 4;
+        const uint32_t base = g * (4 * M) + q * M;
+        const uint32_t rot = g + 16u * q;
 #pragma unroll
         for (int j = 0; j < CPW; ++j) {
             const int t = w * CPW + j;
-            const uint32_t slot = base + (((uint32_t)t + rot) & (uint32_t)(2 * M - 1));
+            const uint32_t slot = base + (((uint32_t)t + rot) & (uint32_t)(M - 1));
             e[j] = lds_load(A, slot * 8u);
         }
         __syncthreads();  // all groups read before any slot is overwritten

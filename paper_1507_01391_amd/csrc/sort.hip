@@ -207,11 +207,11 @@ __constant__ WidePhase kThm2Wide[13] = {
 
 // LDS words of the wide kernel: the largest of the cross-wavefront moves (one 32-bit
 // plane of 64 x m items; the final move pitches rows at m + 1 words), the per-wavefront
-// transpose arrays, and the exchange buffers (16 registers of 64 bits per lane and
+// transpose arrays, and the exchange buffers (XCH registers of 64 bits per lane and
 // wavefront).
 template <int H>
 constexpr int wide_words() {
-    constexpr int a = 64 * (64 * H + 1), b = H * MOVE_WORDS, c = H * 16 * 64 * 2;
+    constexpr int a = 64 * (64 * H + 1), b = H * MOVE_WORDS, c = H * XCH * 64 * 2;
     return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 

@@ -242,39 +242,47 @@ def test_unskewed_transpose_would_conflict(sim):
 
 @pytest.mark.parametrize("m", [64, 128, 256])
 def test_router_placement_conflict_free(sim, m):
-    """Placement of the bank router: group g (2m slots) holds the items bound for
-    destination class g (dst mod 32, the bank pair of a 64-bit slot).  Step t: lane l
-    reads slot 2m (l mod 32) + ((t + (l mod 32) + m (l / 32)) mod 2m) (64-bit reads,
-    32-lane phases over 64 banks) and writes it to its destination, a slot congruent to
-    l modulo 32 (64-bit writes, 16-lane phases).  Over the m steps the two lanes of a
-    group read each of its 2m slots exactly once."""
+    """Placement of the bank router: group g (4m slots) holds the items bound for
+    destination class g (dst mod 16).  Lane l = 16q + g takes quarter q of group g: in
+    step t it reads slot 4m g + q m + ((t + g + 16 q) mod m) (64-bit reads, 32-lane phases
+    over 64 banks) and writes it to its destination, a slot congruent to g modulo 16
+    (64-bit writes, 16-lane phases).  Over the m steps the four lanes of a group read
+    each of its 4m slots exactly once."""
     rd = sim.BankModel(64, 32, 2)
     wr = sim.BankModel(64, 16, 2)
     rng = np.random.default_rng(m)
     seen = np.zeros(64 * m, dtype=int)
     for t in range(m):
-        slots = [2 * m * (l % 32) + ((t + l % 32 + m * (l // 32)) % (2 * m)) for l in range(64)]
+        slots = [4 * m * (l % 16) + m * (l // 16) + ((t + l % 16 + 16 * (l // 16)) % m) for l in range(64)]
         for sl in slots:
             seen[sl] += 1
         assert sim.step_conflicts([(l, 2 * s) for l, s in enumerate(slots)], rd, is_read=True) == 0
-        dst = [32 * int(rng.integers(0, 2 * m)) + l % 32 for l in range(64)]
+        dst = [16 * int(rng.integers(0, 4 * m)) + l % 16 for l in range(64)]
         assert sim.step_conflicts([(l, 2 * s) for l, s in enumerate(dst)], wr, is_read=False) == 0
     assert (seen == 1).all()
 
 
-def test_router_five_class_splits_group_by_class():
-    """Five MSD binary splits on the class bits (dst mod 32, top of the key) leave group
-    g = slots [2m g, 2m (g + 1)) holding exactly the items of class g, for any
-    permutation: the splits are stable partitions on the key's top five bits."""
+def test_router_placement_needs_sixteen_classes(sim):
+    """With eight classes lanes l and l + 8 of one 16-lane write phase carry the same
+    class, and destinations 8 apart modulo 32 can meet: some write conflicts."""
+    wr = sim.BankModel(64, 16, 2)
+    dst = [32 * l + (l % 8) for l in range(64)]     # lanes l, l + 8: residues equal mod 32
+    assert sim.step_conflicts([(l, 2 * s) for l, s in enumerate(dst)], wr, is_read=False) > 0
+
+
+def test_router_class_splits_group_by_class():
+    """Four MSD binary splits on the class bits (dst mod 16, top of the key) leave group
+    g = slots [4m g, 4m (g + 1)) holding exactly the items of class g, for any
+    permutation: the splits are stable partitions on the key's top four bits."""
     rng = np.random.default_rng(5)
     for n in (4096, 8192, 16384):
         dst = rng.permutation(n)
-        key = ((dst % 32) << 27) | ((dst // 32) << 18) | np.arange(n)
-        order = np.argsort(key >> 27, kind="stable")
-        groups = (dst[order] % 32).reshape(32, n // 32)
-        assert (groups == np.arange(32)[:, None]).all()
+        key = ((dst % 16) << 28) | ((dst // 16) << 18) | np.arange(n)
+        order = np.argsort(key >> 28, kind="stable")
+        groups = (dst[order] % 16).reshape(16, n // 16)
+        assert (groups == np.arange(16)[:, None]).all()
         # the key round-trips the destination and the source
-        back = (((key >> 18) & 0x1FF) << 5) | (key >> 27)
+        back = (((key >> 18) & 0x3FF) << 4) | (key >> 28)
         assert np.array_equal(back, dst) and np.array_equal(key & 0x3FFF, np.arange(n))
 
 

@@ -16,8 +16,11 @@ MOVE_WORDS = 64 * 65
 LANES = np.arange(64)
 
 
+XCH = 32   # registers per exchange round
+
+
 def wide_words(H):
-    return max(64 * (64 * H + 1), H * MOVE_WORDS, H * 16 * 64 * 2)
+    return max(64 * (64 * H + 1), H * MOVE_WORDS, H * XCH * 64 * 2)
 
 
 def move_dst(move, M, L, c):
@@ -90,12 +93,12 @@ def test_wide_moves_bijective_in_bounds_conflict_free(H, move):
 
 @pytest.mark.parametrize("H", [2, 4, 8])
 def test_wide_exchange_slots(H):
-    """Exchange of 16 registers between wavefronts as 64-bit words: slot (16 h + j) 64 + L;
+    """Exchange of XCH registers between wavefronts as 64-bit words: slot (XCH h + j) 64 + L;
     64-bit writes are served 16 lanes at a time, reads 32 lanes at a time, over 64 banks."""
     top = 0
     for h in range(H):
-        for j in range(16):
-            slots = [(16 * h + j) * 64 + L for L in range(64)]
+        for j in range(XCH):
+            slots = [(XCH * h + j) * 64 + L for L in range(64)]
             top = max(top, 2 * max(slots) + 1)
             for ph in range(0, 64, 16):    # writes: 16 slots = 32 consecutive words
                 wd = {(2 * s) % 64 for s in slots[ph:ph + 16]}
@@ -299,8 +302,8 @@ def test_bitonic_wide_data_flow_sorts(H, n, hi):
 
 
 def test_wide_exchange_slots_fit_the_transpose_arrays():
-    """The exchange buffer of H wavefronts (16 H x 64 slots of 64 bits) fits in the H
+    """The exchange buffer of H wavefronts (XCH H x 64 slots of 64 bits) fits in the H
     transpose arrays the wide bitonic sort allocates, for H up to 8."""
     for H in (2, 4, 8):
-        top = 2 * ((16 * (H - 1) + 15) * 64 + 63) + 1
+        top = 2 * ((XCH * (H - 1) + XCH - 1) * 64 + 63) + 1
         assert top < H * MOVE_WORDS
