@@ -81,10 +81,10 @@ def _repeat(fn, reps: int) -> None:
 
 
 def run_partition(a):
-    labels, payload, off = inputs.partition(num_tiles=a.tiles)
+    labels, payload, off = inputs.partition(num_tiles=a.tiles, n=a.n)
     dl, dp, do = _dev(labels), _dev(payload), _dev(off)
     lo, po = torch.empty_like(dl), torch.empty_like(dp)
-    _repeat(lambda: ops.tile_partition(dl, dp, do, 64, max_tile_len=4096, schedule=a.schedule,
+    _repeat(lambda: ops.tile_partition(dl, dp, do, 64, max_tile_len=a.n, schedule=a.schedule,
                                        labels_out=lo, payload_out=po), a.reps)
 
 
@@ -178,6 +178,7 @@ def main(argv=None):
     p = sub.add_parser("partition")
     p.add_argument("--schedule", default="split")
     p.add_argument("--tiles", type=int, default=16384)
+    p.add_argument("--n", type=int, default=4096)
     p = sub.add_parser("permute")
     p.add_argument("--schedule", default="split")
     p.add_argument("--direction", default="scatter", choices=["scatter", "gather"])
