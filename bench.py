@@ -68,8 +68,8 @@ MEASURED = {
            "lds_insts": 37748736, "lds_active": 167772160, "lds_conflicts": 0},
     "c4": {"profile": "profiles/merge_c4_counters.md",
            "sources": [KSRC + "merge.hip", KSRC + "bitonic.hpp", KSRC + "common.hpp"],
-           "sha256_prefix": "24a8ade22f7f8218", "knobs": {"merge_wide": 32768},
-           "fetch": 2807199 * 2 * 1024, "write": 8178874 * 1024,
+           "sha256_prefix": "b290cd8f5382d662", "knobs": {"merge_wide": 32768},
+           "fetch": 2804836 * 2 * 1024, "write": 8176982 * 1024,
            "lds_insts": 582923358, "lds_active": 2533340340, "lds_conflicts": 0},
     "c5": {"profile": "profiles/sort_payload_c5_counters.md",
            "sources": [KSRC + "partition.hip", KSRC + "permute.hip", KSRC + "route.hpp", KSRC + "common.hpp",
