@@ -35,7 +35,7 @@ KNOBS = {
     "merge_wide": ([32768, 16384, 8192, 4096], 32768),
     "oneshot": ([1, 0], 1),
     "partition_waves_4096": ([168, 176, 166, 164, 106, 108, 104], 168),
-    "permute_variant": ([6, 7, 8, 9, 1, 0, 2], 6),
+    "permute_variant": ([6, 7, 8, 9, 10, 11, 1, 0, 2], 6),
 }
 
 
@@ -186,16 +186,20 @@ def tune(quick: bool = False, log=print) -> dict:
         lambda: ops.tile_partition(d_lab, d_pay, d_off, 64, max_tile_len=4096, schedule="naive",
                                    labels_out=lo_, payload_out=po_), reps)
 
-    # permute: 8192-item tiles, uniform random permutations
+    # permute: 8192-item tiles, uniform random permutations, forward and backward as
+    # autograd.Permute runs them (a scatter writing a 16-bit inverse, a scatter by it)
     tiles = total // 8192
     pi = np.argsort(rng.random((tiles, 8192)), axis=1).astype(np.int32).reshape(-1)
     d_pi = torch.from_numpy(pi).cuda()
     d_x = torch.randn(pi.shape[0], device="cuda")
     d_off = torch.arange(tiles + 1, device="cuda", dtype=torch.int64) * 8192
-    y = torch.empty_like(d_x)
-    choose("permute_variant",
-           lambda v: (lambda: ops.tile_permute(d_x, d_pi, "scatter", d_off, max_tile_len=8192, out=y)),
-           pi.shape[0], set_knob=True)
+    y, gx = torch.empty_like(d_x), torch.empty_like(d_x)
+    inv = torch.empty(pi.shape[0], dtype=torch.int16, device="cuda")
+
+    def fwd_bwd():
+        ops.tile_permute(d_x, d_pi, "scatter", d_off, max_tile_len=8192, out=y, inv_out=inv)
+        ops.tile_permute(y, inv, "scatter", d_off, max_tile_len=8192, out=gx)
+    choose("permute_variant", lambda v: fwd_bwd, 2 * pi.shape[0], set_knob=True)
     baseline["permute_variant"] = _time_ms(
         lambda: ops.tile_permute(d_x, d_pi, "scatter", d_off, max_tile_len=8192, out=y,
                                  schedule="naive"), reps)
