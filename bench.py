@@ -63,9 +63,9 @@ MEASURED = {
            "lds_insts": 56623104, "lds_active": 163577856, "lds_conflicts": 0},
     "c3": {"profile": "profiles/permute_c3_counters.md",
            "sources": [KSRC + "permute.hip", KSRC + "route.hpp", KSRC + "common.hpp"],
-           "sha256_prefix": None, "knobs": {"permute_variant": 11},
-           "fetch": 919709 * 2 * 1024, "write": 1310737 * 1024,
-           "lds_insts": 37748736, "lds_active": 167772160, "lds_conflicts": 0},
+           "sha256_prefix": "2e5f6df73069899e", "knobs": {"permute_variant": 11},
+           "fetch": 919784 * 2 * 1024, "write": 1310850 * 1024,
+           "lds_insts": 35127296, "lds_active": 162529280, "lds_conflicts": 0},
     "c4": {"profile": "profiles/merge_c4_counters.md",
            "sources": [KSRC + "merge.hip", KSRC + "bitonic.hpp", KSRC + "common.hpp"],
            "sha256_prefix": "b290cd8f5382d662", "knobs": {"merge_wide": 32768},
