@@ -15,13 +15,31 @@ constexpr int R = 64;  // registers (columns) per lane
 // alive at once (register pressure above 256 and a single wave per SIMD).
 TS_DEV void stage_fence() {}
 
+// Composites are 64-bit integers below 2^62.  Read as IEEE doubles such bit patterns are
+// non-negative and finite (subnormal below 2^52) and order exactly like the integers, so
+// the smaller and larger of two composites are one v_min_f64 and one v_max_f64 each:
+// two instructions per compare-exchange where a 64-bit integer compare and four 32-bit
+// selects take five.  No rounding is involved (min and max return one operand's bits)
+// and the kernels keep fp64 subnormals (the default float mode), so the bits come back
+// unchanged.  Written as assembly: the compiler's own min and max first quiet possible
+// signalling NaNs, one more instruction per operand.
+constexpr uint64_t COMP_MASK = (uint64_t(1) << 62) - 1;  // x ^ COMP_MASK reverses the order
+
+TS_DEV uint64_t comp_min(uint64_t a, uint64_t b) {
+    uint64_t r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+TS_DEV uint64_t comp_max(uint64_t a, uint64_t b) {
+    uint64_t r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 TS_DEV void cas(uint64_t& a, uint64_t& b) {  // afterwards a <= b
-    // One 64-bit compare into a lane mask and four selects.  (Written with min/max
-    // the compiler emits two compares per pair.)
-    const uint64_t swap = ballot(b < a);
-    const uint32_t alo = lo32(a), ahi = hi32(a), blo = lo32(b), bhi = hi32(b);
-    a = pack(select_by_mask(swap, ahi, bhi), select_by_mask(swap, alo, blo));
-    b = pack(select_by_mask(swap, bhi, ahi), select_by_mask(swap, blo, alo));
+    const uint64_t lo = comp_min(a, b), hi = comp_max(a, b);
+    a = lo;
+    b = hi;
 }
 
 // One stage of a bitonic network on the register index: pairs (i, i ^ J); ascending
@@ -141,7 +159,7 @@ TS_DEV void layout_move(uint32_t* A, uint64_t (&v)[R], int move, int lane_in) {
 
 // Lanes whose bit `b` is set get an all-ones mask (complemented composites sort in
 // the reverse order).
-TS_DEV uint64_t lane_bit_mask(int lane, int b) { return ((lane >> b) & 1) ? ~0ull : 0ull; }
+TS_DEV uint64_t lane_bit_mask(int lane, int b) { return ((lane >> b) & 1) ? COMP_MASK : 0ull; }
 
 // Level 2^(6+KB) of the bitonic sort below (KB = 1 .. 6).
 template <int KB>
@@ -203,11 +221,15 @@ TS_DEV void cross_wave_stage(uint64_t* X, uint64_t (&v)[R], int h, int hp, bool 
         __syncthreads();
 #pragma unroll
         for (int j0 = 0; j0 < XCH; j0 += 16) {  // 16 partner registers in flight at a time
+            uint64_t y[16];
 #pragma unroll
-            for (int j = j0; j < j0 + 16; ++j) {
-                const uint64_t y = X[(XCH * hp + j) * 64 + lane];
-                const uint64_t x = v[g + j];
-                v[g + j] = keep_min ? (y < x ? y : x) : (y < x ? x : y);
+            for (int j = 0; j < 16; ++j) y[j] = X[(XCH * hp + j0 + j) * 64 + lane];
+            if (keep_min) {  // wave-uniform
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[g + j0 + j] = comp_min(v[g + j0 + j], y[j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[g + j0 + j] = comp_max(v[g + j0 + j], y[j]);
             }
         }
     }
@@ -232,7 +254,7 @@ template <int H>
 TS_DEV void bitonic_sort_wide(uint32_t* A, uint64_t (&v)[R], int h, int lane) {
     uint64_t* X = (uint64_t*)A;
     uint32_t* Aw = A + h * MOVE_WORDS;
-    const uint64_t m0 = (h & 1) ? ~0ull : 0ull;
+    const uint64_t m0 = (h & 1) ? COMP_MASK : 0ull;
     xor_all(v, m0);
     bitonic_sort4096(Aw, v, lane);
     xor_all(v, m0);
@@ -243,7 +265,7 @@ TS_DEV void bitonic_sort_wide(uint32_t* A, uint64_t (&v)[R], int h, int lane) {
 #pragma unroll
         for (int b = k - 1; b >= 0; --b) cross_wave_stage(X, v, h, h ^ (1 << b), asc, lane);
         __syncthreads();  // the exchange buffer overlaps the transpose arrays
-        const uint64_t m = asc ? 0ull : ~0ull;
+        const uint64_t m = asc ? 0ull : COMP_MASK;
         xor_all(v, m);
         bitonic_merge4096(Aw, v, lane);
         xor_all(v, m);

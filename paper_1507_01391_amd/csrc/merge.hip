@@ -14,10 +14,12 @@
 // a time: a merge-path co-rank search picks the A and B ranges that produce them, A is
 // loaded ascending and B descending (a bitonic sequence) and 12 merge stages sort it.
 //
-// Items are 64-bit composites  slot << 60 | key << 28 | position,  distinct within a
-// tile, so the result is the unique stable order.  `slot` packs up to eight tiles of at
-// most 512 keys (four of 1024, two of 2048) into one wavefront: each tile owns a slot of
-// 4096 / P positions and its padding sorts to the end of its slot.
+// Items are 64-bit composites  key << 28 | position,  distinct within a tile, so the
+// result is the unique stable order.  A packing wavefront holds up to eight tiles of at
+// most 512 keys (four of 1024, two of 2048): there the composite is
+// slot << 44 | key << 12 | position, each tile owning a slot of 4096 / P positions,
+// and its padding sorts to the end of its slot.  Both forms stay below 2^62, the range
+// the networks of bitonic.hpp compare in.
 //
 // Sequence of launches (all on one stream, no host synchronisation):
 //   1. clear the work counters (a fill kernel, so the sequence stays capturable);
@@ -40,9 +42,8 @@ using namespace bt;
 
 constexpr int K = MERGE_PIECE;
 constexpr int POS_BITS = MERGE_POS_BITS;
-constexpr uint64_t POS_MASK = (uint64_t(1) << POS_BITS) - 1;
-constexpr int SLOT_SHIFT = 60;  // slot (3 bits) above key and position
-constexpr uint64_t PAD = ~uint64_t(0);
+constexpr int PACKED_POS_BITS = 12;  // positions within a packing wavefront (< 4096)
+constexpr uint64_t PAD = COMP_MASK;  // above every composite
 
 int g_merge_pack = 1;
 // Longest tile sorted whole by one workgroup (4096: none, every longer tile goes
@@ -55,11 +56,15 @@ int g_merge_wide = 32768;
 constexpr int NUM_BINS = 7;
 TS_DEV int bin_counter(int b) { return b < 4 ? b : b + 1; }
 
+// Composite with PB position bits: slot << (32 + PB) | key << PB | pos.
+template <int PB>
 TS_DEV uint64_t make_comp(uint32_t slot, uint32_t key, uint32_t pos) {
-    return ((uint64_t)slot << SLOT_SHIFT) | ((uint64_t)key << POS_BITS) | pos;
+    return ((uint64_t)slot << (32 + PB)) | ((uint64_t)key << PB) | pos;
 }
-TS_DEV uint32_t comp_key(uint64_t c) { return (uint32_t)(c >> POS_BITS); }
-TS_DEV uint32_t comp_pos(uint64_t c) { return (uint32_t)(c & POS_MASK); }
+template <int PB>
+TS_DEV uint32_t comp_key(uint64_t c) { return (uint32_t)(c >> PB); }
+template <int PB>
+TS_DEV uint32_t comp_pos(uint64_t c) { return (uint32_t)c & ((1u << PB) - 1u); }
 
 TS_DEV uint64_t entry(int64_t tile, uint32_t j) { return ((uint64_t)tile << 16) | j; }
 TS_DEV int64_t entry_tile(uint64_t e) { return (int64_t)(e >> 16); }
@@ -140,8 +145,9 @@ __global__ __launch_bounds__(256) void merge_bin_kernel(MergeArgs a) {
 // time, every load of a group issued before any is used (a load per register inside
 // its own branch would wait for each one in turn).
 // `narrow`: every payload offset of the tile (position x elem_stride x 4 bytes) fits
-// in 32 bits, so gathers use a wave-uniform base plus 32-bit offsets.
-template <int NC>
+// in 32 bits, so gathers use a wave-uniform base plus 32-bit offsets.  PB: position
+// bits of the composites.
+template <int NC, int PB = POS_BITS>
 TS_DEV void store_final_regs(const SortArgs& s, int64_t o, int64_t rb, int nvalid,
                              const uint64_t (&v)[R], int c0, int lane, bool narrow) {
     const int ln = (int)opaque((uint32_t)lane);
@@ -153,15 +159,15 @@ TS_DEV void store_final_regs(const SortArgs& s, int64_t o, int64_t rb, int nvali
     // live
     uint32_t pos_of[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) pos_of[c] = comp_pos(v[c0 + c]);
+    for (int c = 0; c < NC; ++c) pos_of[c] = comp_pos<PB>(v[c0 + c]);
     if (s.keys_out) {
         const rsrc_t r = buffer_rsrc(s.keys_out + o + rb, nv * 4u);
         if (s.f32) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) buffer_store(r, off + 256u * c, ordered_to_f32(comp_key(v[c0 + c])));
+            for (int c = 0; c < NC; ++c) buffer_store(r, off + 256u * c, ordered_to_f32(comp_key<PB>(v[c0 + c])));
         } else {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) buffer_store(r, off + 256u * c, comp_key(v[c0 + c]));
+            for (int c = 0; c < NC; ++c) buffer_store(r, off + 256u * c, comp_key<PB>(v[c0 + c]));
         }
     }
     if (s.perm_out) {
@@ -263,7 +269,8 @@ TS_DEV void load_packed(uint32_t* A, uint64_t (&v)[R], const MergeArgs& a, int b
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const uint32_t i = (uint32_t)(64 * c + lane);
-        v[c] = make_comp((uint32_t)(c / CPS), lds_load(A, i * 4u), (uint32_t)(64 * (c % CPS) + lane));
+        v[c] = make_comp<PACKED_POS_BITS>((uint32_t)(c / CPS), lds_load(A, i * 4u),
+                                            (uint32_t)(64 * (c % CPS) + lane));
     }
 }
 
@@ -276,7 +283,7 @@ TS_DEV void store_packed(const uint64_t (&v)[R], const MergeArgs& a, int bin, ui
         int64_t o;
         int n;
         bin_tile(a, bin, cnt, item * P + sl, o, n);
-        store_final_regs<CPS>(a.s, o, 0, n, v, sl * CPS, lane, narrow_payload(a));
+        store_final_regs<CPS, PACKED_POS_BITS>(a.s, o, 0, n, v, sl * CPS, lane, narrow_payload(a));
     }
 }
 
@@ -316,7 +323,7 @@ void merge_sort_kernel(MergeArgs a) {
 #pragma unroll
             for (int c = 0; c < R; ++c) {
                 const uint32_t i = (uint32_t)(64 * c + lane);
-                v[c] = make_comp(0u, lds_load(A, i * 4u), base + i);
+                v[c] = make_comp<POS_BITS>(0u, lds_load(A, i * 4u), base + i);
             }
         }
         bitonic_sort4096(A, v, lane);
@@ -361,7 +368,7 @@ void merge_wide_kernel(MergeArgs a) {
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             const uint32_t i = (uint32_t)(64 * c + lane);
-            v[c] = make_comp(0u, lds_load(Aw, i * 4u), (uint32_t)(4096 * h) + i);
+            v[c] = make_comp<POS_BITS>(0u, lds_load(Aw, i * 4u), (uint32_t)(4096 * h) + i);
         }
         bitonic_sort_wide<H>(A, v, h, lane);
         store_final_regs<R>(a.s, o, 4096 * h, nw, v, 0, lane, narrow_payload(a));

@@ -5,8 +5,8 @@
 // tile is the paper's w x m matrix with w = 64 rows (banks): for m = 64 lane L holds
 // "row" L in 64 registers; for m = 128 and 256 the row is spread over H = m / 64
 // wavefronts, wavefront h holding columns 64h .. 64h + 63 of every row.  Items are
-// 64-bit composites (ordered key << 32 | tile position), all distinct, so any correct
-// sort is the unique stable order.
+// 64-bit composites (ordered key << 30 | tile position, below 2^62 as the networks of
+// bitonic.hpp require), all distinct, so any correct sort is the unique stable order.
 //
 // The schedules share these building blocks:
 //  * a row sort: every lane sorts its 64 registers with a bitonic network
@@ -45,6 +45,12 @@ namespace {
 
 using namespace bt;
 
+// Composite of an ordered key and its tile position (< 2^30).
+constexpr int SORT_POS_BITS = 30;
+TS_DEV uint64_t comp(uint32_t key, uint32_t pos) { return ((uint64_t)key << SORT_POS_BITS) | pos; }
+TS_DEV uint32_t comp_key(uint64_t c) { return (uint32_t)(c >> SORT_POS_BITS); }
+TS_DEV uint32_t comp_pos(uint64_t c) { return (uint32_t)c & ((1u << SORT_POS_BITS) - 1u); }
+
 // One phase of a schedule: xor with `pre`, row sort, xor with `post`, then a layout
 // move.
 struct Phase {
@@ -61,7 +67,7 @@ TS_DEV uint64_t mask_of(int kind, int lane) {
     else if (kind == 2) on = (lane >> 3) & 1;
     else if (kind == 3) on = ((lane & 1) ^ ((lane >> 3) & 1)) != 0;
     else on = (lane >> (kind - 8)) & 1;
-    return on ? ~0ull : 0ull;
+    return on ? COMP_MASK : 0ull;
 }
 
 // Theorem 2 (w = m = 64, super-rows of 8 rows): 13 row sorts.
@@ -144,7 +150,7 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             const uint32_t i = (uint32_t)(64 * c + lane);
-            v[c] = pack(lds_load(A, i * 4u), i);
+            v[c] = comp(lds_load(A, i * 4u), i);
         }
 
         if (SCHED == 2) {
@@ -167,15 +173,15 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         for (int c = 0; c < R; ++c) {
             const int r = 64 * c + sl;
             if (r < n) {
-                const uint32_t key = hi32(v[c]);
+                const uint32_t key = comp_key(v[c]);
                 if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
-                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)lo32(v[c]));
+                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)comp_pos(v[c]));
             }
         }
         if (a.fuse_pay) {
             uint32_t pos[R];
 #pragma unroll
-            for (int c = 0; c < R; ++c) pos[c] = lo32(v[c]);
+            for (int c = 0; c < R; ++c) pos[c] = comp_pos(v[c]);
             gather_payload<R>(a, o, n, pos, lane, [](int c, int ln) { return 64 * c + ln; });
         }
     }
@@ -225,7 +231,7 @@ TS_DEV void wide_row_merge(uint64_t* X, uint64_t (&v)[R], int h, int lane) {
     // level 128: pairs of wavefronts; with H = 4 the second pair merges descending
     const bool asc128 = (H == 2) || ((h >> 1) & 1) == 0;
     cross_wave_stage(X, v, h, h ^ 1, asc128, lane);
-    const uint64_t m2 = asc128 ? 0ull : ~0ull;
+    const uint64_t m2 = asc128 ? 0ull : COMP_MASK;
     xor_all(v, m2);
     row_merge(v);
     xor_all(v, m2);
@@ -336,7 +342,7 @@ void thm2_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         uint64_t v[R];
 #pragma unroll
         for (int c = 0; c < R; ++c)
-            v[c] = pack(lds_load(Aw, (uint32_t)(64 * c + lane) * 4u), (uint32_t)(64 * (64 * h + c) + lane));
+            v[c] = comp(lds_load(Aw, (uint32_t)(64 * c + lane) * 4u), (uint32_t)(64 * (64 * h + c) + lane));
 
 #pragma unroll 1
         for (int p = 0; p < 13; ++p) {
@@ -344,7 +350,7 @@ void thm2_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
             // one register sort per phase: a column, or this wavefront's part of a row
             // (descending in odd wavefronts, for the merge across wavefronts)
             const bool row = ph.sort == SORT_ROW;
-            const uint64_t m1 = (row && (h & 1)) ? ~0ull : 0ull;
+            const uint64_t m1 = (row && (h & 1)) ? COMP_MASK : 0ull;
             xor_all(v, mask_of(ph.pre, lane) ^ m1);
             row_sort(v);
             xor_all(v, m1);
@@ -360,15 +366,15 @@ void thm2_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         for (int c = 0; c < R; ++c) {
             const int r = 64 * (cb + c) + sl;
             if (r < n) {
-                const uint32_t key = hi32(v[c]);
+                const uint32_t key = comp_key(v[c]);
                 if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
-                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)lo32(v[c]));
+                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)comp_pos(v[c]));
             }
         }
         if (a.fuse_pay) {
             uint32_t pos[R];
 #pragma unroll
-            for (int c = 0; c < R; ++c) pos[c] = lo32(v[c]);
+            for (int c = 0; c < R; ++c) pos[c] = comp_pos(v[c]);
             gather_payload<R>(a, o, n, pos, lane, [cb](int c, int ln) { return 64 * (cb + c) + ln; });
         }
     }
@@ -418,7 +424,7 @@ void bitonic_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         uint64_t v[R];
 #pragma unroll
         for (int c = 0; c < R; ++c)
-            v[c] = pack(lds_load(Aw, (uint32_t)(64 * c + lane) * 4u), (uint32_t)(4096 * h + 64 * c + lane));
+            v[c] = comp(lds_load(Aw, (uint32_t)(64 * c + lane) * 4u), (uint32_t)(4096 * h + 64 * c + lane));
 
         bitonic_sort_wide<H>(A, v, h, lane);
 
@@ -429,15 +435,15 @@ void bitonic_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         for (int c = 0; c < R; ++c) {
             const int r = rb + 64 * c + sl;
             if (r < n) {
-                const uint32_t key = hi32(v[c]);
+                const uint32_t key = comp_key(v[c]);
                 if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
-                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)lo32(v[c]));
+                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)comp_pos(v[c]));
             }
         }
         if (a.fuse_pay) {
             uint32_t pos[R];
 #pragma unroll
-            for (int c = 0; c < R; ++c) pos[c] = lo32(v[c]);
+            for (int c = 0; c < R; ++c) pos[c] = comp_pos(v[c]);
             gather_payload<R>(a, o, n, pos, lane, [rb](int c, int ln) { return rb + 64 * c + ln; });
         }
     }
