@@ -68,15 +68,15 @@ MEASURED = {
            "lds_insts": 35127296, "lds_active": 162529280, "lds_conflicts": 0},
     "c4": {"profile": "profiles/merge_c4_counters.md",
            "sources": [KSRC + "merge.hip", KSRC + "bitonic.hpp", KSRC + "common.hpp"],
-           "sha256_prefix": None, "knobs": {"merge_wide": 32768},
-           "fetch": 2804836 * 2 * 1024, "write": 8176982 * 1024,
-           "lds_insts": 582923358, "lds_active": 2533340340, "lds_conflicts": 0},
+           "sha256_prefix": "98861c8132c41baf", "knobs": {"merge_wide": 32768},
+           "fetch": 2720490 * 2 * 1024, "write": 7981658 * 1024,
+           "lds_insts": 584708366, "lds_active": 2526200308, "lds_conflicts": 0},
     "c5": {"profile": "profiles/sort_payload_c5_counters.md",
            "sources": [KSRC + "sort.hip", KSRC + "bitonic.hpp", KSRC + "permute.hip", KSRC + "route.hpp",
                        KSRC + "common.hpp", KSRC + "api.cpp", "paper_1507_01391_amd/autograd.py"],
-           "sha256_prefix": None, "knobs": {"sort_plan_16384": 3, "oneshot": 1},
-           "fetch": 2670155 * 2 * 1024, "write": 5163518 * 1024,
-           "lds_insts": 192937984, "lds_active": 824180736, "lds_conflicts": 0},
+           "sha256_prefix": "7349a8b8b0d6d35a", "knobs": {"sort_plan_16384": 3, "oneshot": 1},
+           "fetch": 2680086 * 2 * 1024, "write": 5162382 * 1024,
+           "lds_insts": 161579008, "lds_active": 786038784, "lds_conflicts": 0},
 }
 
 

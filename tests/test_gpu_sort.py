@@ -289,6 +289,24 @@ def test_thm2_wide_f32_and_edges(ts, oracle, cap):
     run_and_compare(ts, oracle, x.view(np.uint32), None, off, "thm2", max_len=cap, f32=True)
 
 
+# Keys at the edges of the range the sorting networks compare composites in, read as
+# IEEE doubles: key 0 at position 0 is +0.0, keys below 2^22 give subnormal composites,
+# 2^22 is the first normal one, and the top bit and all-ones keys give the largest.
+EDGE_KEYS = np.array([0, 1, 2, 3, 2**21, 2**22 - 1, 2**22, 2**22 + 1, 2**30, 2**31 - 1, 2**31,
+                      2**31 + 1, 0xFFFFFFFE, 0xFFFFFFFF], np.uint32)
+
+
+@pytest.mark.parametrize("schedule,max_len", [("bitonic", 4096), ("thm2", 4096), ("bitonic", 16384),
+                                              ("thm2", 16384), ("merge", 65536)])
+def test_composite_range_edge_keys(ts, oracle, schedule, max_len):
+    rng = np.random.default_rng(41)
+    sizes = [s for s in (1, 2, 300, 1000, 4096, 4097, 9000, 16384, 20000, 32768, 40000) if s <= max_len]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    keys = rng.choice(EDGE_KEYS, size=int(off[-1]))
+    payload = np.arange(off[-1], dtype=np.uint32)
+    run_and_compare(ts, oracle, keys, payload, off, schedule, max_len=max_len)
+
+
 def test_thm2_tile_longer_than_capacity_is_reported(ts):
     from tests.gpu_util import dev
     keys = np.zeros(16385, np.uint32)
