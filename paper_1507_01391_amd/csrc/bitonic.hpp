@@ -157,20 +157,52 @@ TS_DEV void layout_move(uint32_t* A, uint64_t (&v)[R], int move, int lane_in) {
     wave_lds_fence();  // later writes of A stay after these reads
 }
 
-// Lanes whose bit `b` is set get an all-ones mask (complemented composites sort in
-// the reverse order).
-TS_DEV uint64_t lane_bit_mask(int lane, int b) { return ((lane >> b) & 1) ? COMP_MASK : 0ull; }
+// The transposes of the bitonic sort below, with lane reversal: in the transposed
+// layout register r (a row) keeps column c at lane c, or at lane 63 - c when bit KB-1
+// of r is set (the upper half of every block of 2^KB rows).  TO_ROWS = false: from the
+// row layout (lane = row, register = column) to that layout; true: back.  The reversal
+// only changes which lane-dependent base an access adds its immediate offset to
+// (lane or 63 - lane), and a 32-lane phase still touches 32 consecutive words of one
+// row (reads) or words 65 apart (writes): no bank conflicts, no extra instructions.
+template <int KB, bool TO_ROWS>
+TS_DEV void transpose_rev(uint32_t* A, uint64_t (&v)[R], int lane_in) {
+#pragma unroll
+    for (int half = 1; half >= 0; --half) {
+        wave_lds_fence();  // earlier reads of A (other lanes' slots) stay before these writes
+        const int lane = (int)opaque((uint32_t)lane_in);
+        const int rlane = 63 - lane;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            // writer: row layout (lane = row, register c = column) or the reversed layout
+            // (register c = row c, this lane = column lane or 63 - lane)
+            const int base = (TO_ROWS && ((c >> (KB - 1)) & 1)) ? rlane : lane;
+            lds_store(A, (uint32_t)(65 * base + c) * 4u, half ? hi32(v[c]) : lo32(v[c]));
+        }
+        wave_lds_fence();  // the reads below see every lane's writes
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int base = (!TO_ROWS && ((c >> (KB - 1)) & 1)) ? rlane : lane;
+            const uint32_t w = lds_load(A, (uint32_t)(65 * c + base) * 4u);
+            v[c] = half ? pack(w, lo32(v[c])) : pack(hi32(v[c]), w);
+        }
+    }
+    wave_lds_fence();  // later writes of A stay after these reads
+}
 
-// Level 2^(6+KB) of the bitonic sort below (KB = 1 .. 6).
+// Level 2^(6+KB) of the bitonic sort below (KB = 1 .. 6) in the form whose first stage
+// compares every item with its mirror image in the block (item i of a block of B
+// against item B-1-i) and whose later stages all sort ascending, so that no row is
+// sorted descending and no composite is complemented.  Item index 64 r + c (row r =
+// lane, column c = register).  In the lane-reversed transposed layout the mirror of
+// (row r, column c), (row r ^ (2^KB - 1), column 63 - c), sits at the same lane.
 template <int KB>
 TS_DEV void bitonic_level(uint32_t* A, uint64_t (&v)[R], int lane) {
-    layout_move(A, v, MOVE_T, lane);  // lane bits become register bits
-    reg_level_stages<KB>(v);
-    layout_move(A, v, MOVE_T, lane);  // back: register bits
-    const uint64_t m = (KB < 6) ? lane_bit_mask(lane, KB) : 0ull;
-    xor_all(v, m);
-    row_merge(v);
-    xor_all(v, m);
+    transpose_rev<KB, false>(A, v, lane);            // rows become registers
+    net_stage<0, (1 << KB) - 1>(v);                  // mirror stage on the row bits
+    stage_fence();
+    if constexpr (KB >= 2) net_stages<0, (1 << (KB - 2))>(v);  // the other row-bit stages
+    transpose_rev<KB, true>(A, v, lane);             // back: columns are registers
+    row_merge(v);                                    // column-bit stages 32 .. 1
     if constexpr (KB < 6) bitonic_level<KB + 1>(A, v, lane);
 }
 
@@ -179,10 +211,7 @@ TS_DEV void bitonic_level(uint32_t* A, uint64_t (&v)[R], int lane) {
 // on register bits run in registers; stages on lane bits run in registers after a
 // conflict-free transpose through A.
 TS_DEV void bitonic_sort4096(uint32_t* A, uint64_t (&v)[R], int lane) {
-    // levels 2 .. 64: rows (lanes) sorted, odd rows descending
-    xor_all(v, lane_bit_mask(lane, 0));
-    row_sort(v);
-    xor_all(v, lane_bit_mask(lane, 0));
+    row_sort(v);                      // levels 2 .. 64: every row ascending
     bitonic_level<1>(A, v, lane);     // levels 128 .. 4096
     layout_move(A, v, MOVE_T, lane);  // to store order
 }
@@ -235,6 +264,50 @@ TS_DEV void cross_wave_stage(uint64_t* X, uint64_t (&v)[R], int h, int hp, bool 
     }
 }
 
+// First stage of a level of the wide sort in mirror form: item i of wavefront h
+// (i = 64 c + L) against item 4095 - i of wavefront hp (register 63 - c, lane 63 - L);
+// the wavefront with the lower index keeps the smaller composite.  Registers go through
+// X in two rounds of 32 closed under c -> 63 - c (round 0: c < 16 and c >= 48; round
+// 1: 16 <= c < 48), register c of lane L at slot (32 h + s(c)) 64 + L with
+// s(63 - c) = 31 - s(c), so both partners read slot 31 - s at lane 63 - L: the same
+// register indices in every wavefront, consecutive slots per phase (reads descending),
+// no bank conflicts.  All H wavefronts take part.
+TS_DEV void cross_wave_mirror(uint64_t* X, uint64_t (&v)[R], int h, int hp, int lane_in) {
+    static_assert(XCH == 32, "two rounds of 32 registers");
+    const bool keep_min = h < hp;  // wave-uniform
+    const int lane = (int)opaque((uint32_t)lane_in);
+    const int rl = 63 - lane;
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        __syncthreads();  // earlier readers of X are done
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const int c = round == 0 ? (j < 16 ? j : j + 32) : j + 16;
+            X[(32 * h + j) * 64 + lane] = v[c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j0 = 0; j0 < 32; j0 += 16) {  // 16 partner registers in flight at a time
+            uint64_t y[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) y[j] = X[(32 * hp + 31 - (j0 + j)) * 64 + rl];
+            if (keep_min) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int jj = j0 + j, c = round == 0 ? (jj < 16 ? jj : jj + 32) : jj + 16;
+                    v[c] = comp_min(v[c], y[j]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int jj = j0 + j, c = round == 0 ? (jj < 16 ? jj : jj + 32) : jj + 16;
+                    v[c] = comp_max(v[c], y[j]);
+                }
+            }
+        }
+    }
+}
+
 // Words of LDS the wide bitonic sort needs: one transpose array per wavefront (the
 // exchange buffer of cross_wave_stage, XCH H x 64 x 2 words, fits in it).
 template <int H>
@@ -245,30 +318,24 @@ constexpr int wide_bitonic_words() {
 
 // Batcher's bitonic sort of 4096 H composites held by H wavefronts (wavefront h = the
 // item indices 4096 h .. 4096 h + 4095).  Every wavefront sorts its own 4096 items
-// (descending in odd wavefronts); each further level compares across wavefronts on the
-// wavefront bits and finishes inside each wavefront with the 12 merge stages of
-// bitonic_merge4096.  On exit register c of lane L in wavefront h holds rank
-// 4096 h + 64 c + L.  A: wide_bitonic_words<H>() words, wavefront h uses its own
+// ascending; each further level (blocks of 2^k wavefronts) starts with the mirror
+// stage against wavefront h ^ (2^k - 1), compares across wavefronts on the lower
+// wavefront bits, and finishes inside each wavefront with the 12 merge stages of
+// bitonic_merge4096, all ascending.  On exit register c of lane L in wavefront h holds
+// rank 4096 h + 64 c + L.  A: wide_bitonic_words<H>() words, wavefront h uses its own
 // MOVE_WORDS part for the transposes.
 template <int H>
 TS_DEV void bitonic_sort_wide(uint32_t* A, uint64_t (&v)[R], int h, int lane) {
     uint64_t* X = (uint64_t*)A;
     uint32_t* Aw = A + h * MOVE_WORDS;
-    const uint64_t m0 = (h & 1) ? COMP_MASK : 0ull;
-    xor_all(v, m0);
     bitonic_sort4096(Aw, v, lane);
-    xor_all(v, m0);
 #pragma unroll
     for (int k = 1; (1 << k) <= H; ++k) {
-        // level 4096 * 2^k: blocks of 2^k wavefronts, ascending where bit k of h is clear
-        const bool asc = ((h >> k) & 1) == 0;
+        cross_wave_mirror(X, v, h, h ^ ((1 << k) - 1), lane);
 #pragma unroll
-        for (int b = k - 1; b >= 0; --b) cross_wave_stage(X, v, h, h ^ (1 << b), asc, lane);
+        for (int b = k - 2; b >= 0; --b) cross_wave_stage(X, v, h, h ^ (1 << b), true, lane);
         __syncthreads();  // the exchange buffer overlaps the transpose arrays
-        const uint64_t m = asc ? 0ull : COMP_MASK;
-        xor_all(v, m);
         bitonic_merge4096(Aw, v, lane);
-        xor_all(v, m);
     }
 }
 

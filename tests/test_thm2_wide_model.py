@@ -245,61 +245,8 @@ def test_wide_kernel_data_flow_01_inputs():
                                   np.argsort(keys, kind="stable"))
 
 
-# ---- the bitonic network spread over H wavefronts (bitonic_sort_wide) -----------------
-
-def bitonic_merge_block(b):
-    """Ascending bitonic merge of every row of b (length 4096, item index 64 c + L):
-    stages 2048 .. 1, as bitonic_merge4096 runs them on registers and lanes."""
-    n = b.shape[-1]
-    j = n // 2
-    idx = np.arange(n)
-    while j >= 1:
-        lo = idx[(idx & j) == 0]
-        hi = lo | j
-        x, y = b[..., lo].copy(), b[..., hi].copy()
-        b[..., lo], b[..., hi] = np.minimum(x, y), np.maximum(x, y)
-        j //= 2
-    return b
-
-
-def run_bitonic_wide(keys, H):
-    """Wavefront h holds items 4096 h .. 4096 h + 4095 (item index 64 c + L); the steps of
-    bitonic_sort_wide: own sort (descending in odd wavefronts), then per level the
-    exchanges across wavefronts and the in-wavefront merge."""
-    n = len(keys)
-    cap = 4096 * H
-    pos = np.arange(cap, dtype=np.uint64)
-    k = np.full(cap, 0xFFFFFFFF, dtype=np.uint64)
-    k[:n] = keys
-    V = ((k << np.uint64(32)) | pos).reshape(H, 4096)
-    for h in range(H):
-        V[h] = np.sort(V[h])[::-1] if h & 1 else np.sort(V[h])
-    k_ = 1
-    while (1 << k_) <= H:
-        for b in range(k_ - 1, -1, -1):
-            W = V.copy()
-            for h in range(H):
-                hp = h ^ (1 << b)
-                asc = ((h >> k_) & 1) == 0
-                keep_min = (h < hp) == asc
-                W[h] = np.minimum(V[h], V[hp]) if keep_min else np.maximum(V[h], V[hp])
-            V = W
-        for h in range(H):
-            asc = ((h >> k_) & 1) == 0
-            m = np.uint64(0) if asc else FULL
-            V[h] = bitonic_merge_block((V[h] ^ m)[None, :])[0] ^ m
-        k_ += 1
-    return V.reshape(-1)[:n]
-
-
-@pytest.mark.parametrize("H,n,hi", [(2, 8192, 2**32), (2, 4097, 5), (4, 16384, 3), (4, 9000, 2**32),
-                                    (8, 32768, 2**32), (8, 16385, 17), (8, 30000, 2)])
-def test_bitonic_wide_data_flow_sorts(H, n, hi):
-    rng = np.random.default_rng(H * 100 + n)
-    keys = rng.integers(0, hi, size=n, dtype=np.uint64).astype(np.uint32)
-    out = run_bitonic_wide(keys, H)
-    assert np.array_equal((out & np.uint64(0xFFFFFFFF)).astype(np.int64), np.argsort(keys, kind="stable"))
-
+# ---- exchange buffer of the bitonic network spread over H wavefronts -----------------
+# (its data flow is modelled in test_bitonic_flip_model.py)
 
 def test_wide_exchange_slots_fit_the_transpose_arrays():
     """The exchange buffer of H wavefronts (XCH H x 64 slots of 64 bits) fits in the H
