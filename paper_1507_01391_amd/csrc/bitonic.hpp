@@ -10,6 +10,16 @@ namespace bt {
 
 constexpr int R = 64;  // registers (columns) per lane
 
+// A 32-bit LDS read that the compiler does not pair with its neighbour into one
+// two-word read: such a pair lands in two adjacent registers, and moving the words into
+// the halves of the 64-bit composites they belong to cost about one extra move and one
+// address add per word (19 % of the sorting kernels' VALU instructions); a volatile
+// access to the LDS address space is issued as it stands.
+TS_DEV uint32_t lds_load_single(const uint32_t* base, uint32_t byte_off) {
+    typedef __attribute__((address_space(3))) volatile const uint32_t lds_word;
+    return *(lds_word*)((__attribute__((address_space(3))) const char*)base + byte_off);
+}
+
 // Keep the instruction scheduler from interleaving consecutive network stages: each
 // stage rewrites all 64 registers in place, and interleaving keeps old and new copies
 // alive at once (register pressure above 256 and a single wave per SIMD).
@@ -150,7 +160,7 @@ TS_DEV void layout_move(uint32_t* A, uint64_t (&v)[R], int move, int lane_in) {
             const uint32_t slot = (move == MOVE_T)
                                       ? (uint32_t)(65 * c + lane)
                                       : (uint32_t)(c * 64 + ((lane + move_skew(move, c)) & 63));
-            const uint32_t w = lds_load(A, slot * 4u);
+            const uint32_t w = lds_load_single(A, slot * 4u);
             v[c] = half ? pack(w, lo32(v[c])) : pack(hi32(v[c]), w);
         }
     }
@@ -182,7 +192,7 @@ TS_DEV void transpose_rev(uint32_t* A, uint64_t (&v)[R], int lane_in) {
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             const int base = (!TO_ROWS && ((c >> (KB - 1)) & 1)) ? rlane : lane;
-            const uint32_t w = lds_load(A, (uint32_t)(65 * c + base) * 4u);
+            const uint32_t w = lds_load_single(A, (uint32_t)(65 * c + base) * 4u);
             v[c] = half ? pack(w, lo32(v[c])) : pack(hi32(v[c]), w);
         }
     }
