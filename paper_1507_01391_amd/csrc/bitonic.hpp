@@ -277,11 +277,11 @@ TS_DEV void cross_wave_stage(uint64_t* X, uint64_t (&v)[R], int h, int hp, bool 
 // First stage of a level of the wide sort in mirror form: item i of wavefront h
 // (i = 64 c + L) against item 4095 - i of wavefront hp (register 63 - c, lane 63 - L);
 // the wavefront with the lower index keeps the smaller composite.  Registers go through
-// X in two rounds of 32 closed under c -> 63 - c (round 0: c < 16 and c >= 48; round
-// 1: 16 <= c < 48), register c of lane L at slot (32 h + s(c)) 64 + L with
-// s(63 - c) = 31 - s(c), so both partners read slot 31 - s at lane 63 - L: the same
-// register indices in every wavefront, consecutive slots per phase (reads descending),
-// no bank conflicts.  All H wavefronts take part.
+// X in two exchange rounds of 32 registers closed under c -> 63 - c (the first takes
+// c < 16 and c >= 48, the second 16 <= c < 48), register c of lane L at slot
+// (32 h + s(c)) 64 + L with s(63 - c) = 31 - s(c), so both partners read slot 31 - s at
+// lane 63 - L: the same register indices in every wavefront, consecutive slots per
+// phase (reads descending), no bank conflicts.  All H wavefronts take part.
 TS_DEV void cross_wave_mirror(uint64_t* X, uint64_t (&v)[R], int h, int hp, int lane_in) {
     static_assert(XCH == 32, "two rounds of 32 registers");
     const bool keep_min = h < hp;  // wave-uniform
