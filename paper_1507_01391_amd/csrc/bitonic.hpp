@@ -34,6 +34,9 @@ TS_DEV void stage_fence() {}
 // unchanged.  Written as assembly: the compiler's own min and max first quiet possible
 // signalling NaNs, one more instruction per operand.
 constexpr uint64_t COMP_MASK = (uint64_t(1) << 62) - 1;  // x ^ COMP_MASK reverses the order
+#if defined(__FAST_MATH__)
+#error "the fp64 min/max compare-exchange needs fp64 subnormals kept: build without fast math"
+#endif
 
 TS_DEV uint64_t comp_min(uint64_t a, uint64_t b) {
     uint64_t r;
