@@ -241,10 +241,11 @@ TS_DEV void bin_tile(const MergeArgs& a, int bin, uint32_t cnt, uint32_t e, int6
 template <int CPS>
 TS_DEV void stage_keys(uint32_t* A, const SortArgs& s, int64_t o, int n, int w0, int lane) {
     constexpr int G = CPS < 16 ? CPS : 16;
+    const rsrc_t rk = buffer_rsrc(s.keys_in + o, (uint32_t)(n > 0 ? n : 0) * 4u);  // 0 past the end
 #pragma unroll 1
     for (int g = 0; g < CPS; g += G) {
         uint32_t kk[G];
-        load_columns<G>(s.keys_in, 1, o, n, g, lane, kk, s.offsets);
+        buffer_load_columns<G>(rk, (uint32_t)lane * 4u + 256u * (uint32_t)g, kk);
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const uint32_t i = (uint32_t)(64 * (g + j) + lane);

@@ -92,6 +92,31 @@ __constant__ Phase kThm2[13] = {
 // rank_of(c), whose source position is pos[c].  Used where no permutation is kept for a
 // second, routed launch (partition through a sort schedule).  Addresses are rebuilt per
 // channel from an opaque lane index, so none stay live across the channel loop.
+// Stores of keys and positions: register c of lane L holds rank rb + 64 c + L, valid
+// below n.  Buffer resources over the ranks rb ..: a column is the lane offset plus an
+// immediate, and stores of ranks >= n are dropped by the hardware range check, so
+// there is no per-register branch or 64-bit address.
+TS_DEV void store_sorted(const SortArgs& a, int64_t o, int rb, int n, const uint64_t (&v)[R], int lane_in) {
+    const int ln = (int)opaque((uint32_t)lane_in);
+    const uint32_t nv = n > rb ? (uint32_t)(n - rb) : 0u;
+    const uint32_t off = (uint32_t)ln * 4u;
+    if (a.keys_out) {
+        const rsrc_t r = buffer_rsrc(a.keys_out + o + rb, nv * 4u);
+        if (a.f32) {
+#pragma unroll
+            for (int c = 0; c < R; ++c) buffer_store(r, off + 256u * c, ordered_to_f32(comp_key(v[c])));
+        } else {
+#pragma unroll
+            for (int c = 0; c < R; ++c) buffer_store(r, off + 256u * c, comp_key(v[c]));
+        }
+    }
+    if (a.perm_out) {
+        const rsrc_t r = buffer_rsrc(a.perm_out + o + rb, nv * 4u);
+#pragma unroll
+        for (int c = 0; c < R; ++c) buffer_store(r, off + 256u * c, comp_pos(v[c]));
+    }
+}
+
 template <int NREG, typename RankFn>
 TS_DEV void gather_payload(const SortArgs& a, int64_t o, int n, const uint32_t (&pos)[NREG], int lane,
                            RankFn rank_of) {
@@ -136,10 +161,11 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         const int n = (int)len;
         // ---- load: 16 coalesced columns at a time, staged through LDS (word 64 c + L);
         // register c of lane L then holds item 64 c + L; padding sorts last
+        const rsrc_t rk = buffer_rsrc(a.keys_in + o, (uint32_t)(n > 0 ? n : 0) * 4u);  // 0 past the end
 #pragma unroll 1
         for (int g = 0; g < R; g += 16) {
             uint32_t kk[16];
-            load_columns<16>(a.keys_in, 1, o, n, g, lane, kk, offs);
+            buffer_load_columns<16>(rk, (uint32_t)lane * 4u + 256u * (uint32_t)g, kk);
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const uint32_t i = (uint32_t)(64 * (g + j) + lane);
@@ -166,18 +192,8 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
             bitonic_sort4096(A, v, lane);
         }
 
-        // ---- store: register c, lane L holds rank 64 c + L (addresses computed here,
-        // not hoisted above the network)
-        const int sl = (int)opaque((uint32_t)lane);
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-            const int r = 64 * c + sl;
-            if (r < n) {
-                const uint32_t key = comp_key(v[c]);
-                if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
-                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)comp_pos(v[c]));
-            }
-        }
+        // ---- store: register c, lane L holds rank 64 c + L
+        store_sorted(a, o, 0, n, v, lane);
         if (a.fuse_pay) {
             uint32_t pos[R];
 #pragma unroll
@@ -328,10 +344,11 @@ void thm2_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         // reads back its own words), which bounds the loads in flight.
         uint32_t* Aw = A + h * MOVE_WORDS;
         __syncthreads();  // every wavefront has read the previous tile's last move
+        const rsrc_t rk = buffer_rsrc(a.keys_in + o, (uint32_t)(n > 0 ? n : 0) * 4u);  // 0 past the end
 #pragma unroll 1
         for (int g = 0; g < R; g += 16) {
             uint32_t kk[16];
-            load_columns<16>(a.keys_in, 1, o, n, 64 * h + g, lane, kk, offs);
+            buffer_load_columns<16>(rk, (uint32_t)lane * 4u + 256u * (uint32_t)(64 * h + g), kk);
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const uint32_t i = (uint32_t)(64 * (64 * h + g + j) + lane);
@@ -360,17 +377,8 @@ void thm2_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         }
 
         // ---- store: register c of lane L in wavefront h holds rank 64 (64 h + c) + L
-        const int sl = (int)opaque((uint32_t)lane);
         const int cb = 64 * h;
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-            const int r = 64 * (cb + c) + sl;
-            if (r < n) {
-                const uint32_t key = comp_key(v[c]);
-                if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
-                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)comp_pos(v[c]));
-            }
-        }
+        store_sorted(a, o, 4096 * h, n, v, lane);
         if (a.fuse_pay) {
             uint32_t pos[R];
 #pragma unroll
@@ -411,10 +419,11 @@ void bitonic_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         // ---- load through this wavefront's own part of A (16 columns in flight)
         uint32_t* Aw = A + h * MOVE_WORDS;
         __syncthreads();  // every wavefront is done with the previous tile's exchanges
+        const rsrc_t rk = buffer_rsrc(a.keys_in + o + 4096 * h, (uint32_t)nw * 4u);  // 0 past the end
 #pragma unroll 1
         for (int g = 0; g < R; g += 16) {
             uint32_t kk[16];
-            load_columns<16>(a.keys_in, 1, o + 4096 * h, nw, g, lane, kk, offs);
+            buffer_load_columns<16>(rk, (uint32_t)lane * 4u + 256u * (uint32_t)g, kk);
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int i = 64 * (g + j) + lane;
@@ -429,17 +438,8 @@ void bitonic_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
         bitonic_sort_wide<H>(A, v, h, lane);
 
         // ---- store: register c of lane L in wavefront h holds rank 4096 h + 64 c + L
-        const int sl = (int)opaque((uint32_t)lane);
         const int rb = 4096 * h;
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-            const int r = rb + 64 * c + sl;
-            if (r < n) {
-                const uint32_t key = comp_key(v[c]);
-                if (a.keys_out) store_item(a.keys_out, 1, o, r, a.f32 ? ordered_to_f32(key) : key);
-                if (a.perm_out) store_item(a.perm_out, 1, o, r, (int32_t)comp_pos(v[c]));
-            }
-        }
+        store_sorted(a, o, rb, n, v, lane);
         if (a.fuse_pay) {
             uint32_t pos[R];
 #pragma unroll
