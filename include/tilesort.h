@@ -120,8 +120,9 @@ enum { TS_OP_SORT = 0, TS_OP_PARTITION = 1, TS_OP_PERMUTE = 2, TS_OP_DEVICE_SORT
  *                         runs in the workspace by it and skips (and flags) a tile
  *                         outside [0, N); the other schedules keep the permutation of a
  *                         payload without perm_out at workspace index = item index.
- * Supported tile length: 16384 for BITONIC, THM2, SPLIT and NAIVE, 2^28 for MERGE; a longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the
- * autotuned plan for max_tile_len up to 4096 / 8192 / 16384 and MERGE beyond.
+ * Supported tile length: 16384 for BITONIC, THM2, SPLIT and NAIVE, 2^28 for MERGE; a
+ * longer max_tile_len returns TS_ERR_UNSUPPORTED.  AUTO takes the autotuned plan for
+ * max_tile_len up to 4096 / 8192 / 16384 and MERGE beyond.
  * The workspace must hold ts_workspace_bytes(TS_OP_SORT, flags, ...) bytes: the
  * merge schedule needs about 16 bytes per key for its runs and work lists, a payload
  * without perm_out (outside the merge schedule) 4 bytes per key for the permutation.
