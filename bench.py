@@ -68,13 +68,13 @@ MEASURED = {
            "lds_insts": 35127296, "lds_active": 162529280, "lds_conflicts": 0},
     "c4": {"profile": "profiles/merge_c4_counters.md",
            "sources": [KSRC + "merge.hip", KSRC + "bitonic.hpp", KSRC + "common.hpp"],
-           "sha256_prefix": "e80b83cf9c582e6b", "knobs": {"merge_wide": 32768},
+           "sha256_prefix": "967d1d22f957b980", "knobs": {"merge_wide": 32768},
            "fetch": 2724705 * 2 * 1024, "write": 7895876 * 1024,
            "lds_insts": 850484778, "lds_active": 2530114548, "lds_conflicts": 0},
     "c5": {"profile": "profiles/sort_payload_c5_counters.md",
            "sources": [KSRC + "sort.hip", KSRC + "bitonic.hpp", KSRC + "permute.hip", KSRC + "route.hpp",
                        KSRC + "common.hpp", KSRC + "api.cpp", "paper_1507_01391_amd/autograd.py"],
-           "sha256_prefix": "d815a636a5e944c4", "knobs": {"sort_plan_16384": 3, "oneshot": 1},
+           "sha256_prefix": "403e26efae9b82d9", "knobs": {"sort_plan_16384": 3, "oneshot": 1},
            "fetch": 2682067 * 2 * 1024, "write": 5161059 * 1024,
            "lds_insts": 180387840, "lds_active": 786300928, "lds_conflicts": 0},
 }

@@ -20,11 +20,6 @@ TS_DEV uint32_t lds_load_single(const uint32_t* base, uint32_t byte_off) {
     return *(lds_word*)((__attribute__((address_space(3))) const char*)base + byte_off);
 }
 
-// Keep the instruction scheduler from interleaving consecutive network stages: each
-// stage rewrites all 64 registers in place, and interleaving keeps old and new copies
-// alive at once (register pressure above 256 and a single wave per SIMD).
-TS_DEV void stage_fence() {}
-
 // Composites are 64-bit integers below 2^62.  Read as IEEE doubles such bit patterns are
 // non-negative and finite (subnormal below 2^52) and order exactly like the integers, so
 // the smaller and larger of two composites are one v_min_f64 and one v_max_f64 each:
@@ -76,7 +71,6 @@ TS_DEV void net_stage(uint64_t (&v)[R]) {
 template <int K, int J>
 TS_DEV void net_stages(uint64_t (&v)[R]) {
     net_stage<K, J>(v);
-    stage_fence();
     if constexpr (J > 1) net_stages<K, J / 2>(v);
 }
 
@@ -92,13 +86,6 @@ TS_DEV void row_sort(uint64_t (&v)[R]) { net_levels<2>(v); }
 
 // Ascending bitonic merge of the 64 registers of every lane (stages 32 .. 1).
 TS_DEV void row_merge(uint64_t (&v)[R]) { net_stages<0, R / 2>(v); }
-
-// Stages j = 2^(KB-1) .. 1 of bitonic level 2^KB on the register index, direction
-// given by bit KB of the register index (ascending when clear).
-template <int KB>
-TS_DEV void reg_level_stages(uint64_t (&v)[R]) {
-    net_stages<(KB < 6 ? (1 << KB) : 0), (1 << (KB - 1))>(v);
-}
 
 TS_DEV void xor_all(uint64_t (&v)[R], uint64_t m) {
 #pragma unroll
@@ -212,7 +199,6 @@ template <int KB>
 TS_DEV void bitonic_level(uint32_t* A, uint64_t (&v)[R], int lane) {
     transpose_rev<KB, false>(A, v, lane);            // rows become registers
     net_stage<0, (1 << KB) - 1>(v);                  // mirror stage on the row bits
-    stage_fence();
     if constexpr (KB >= 2) net_stages<0, (1 << (KB - 2))>(v);  // the other row-bit stages
     transpose_rev<KB, true>(A, v, lane);             // back: columns are registers
     row_merge(v);                                    // column-bit stages 32 .. 1
