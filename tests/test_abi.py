@@ -75,7 +75,7 @@ def test_partition_argument_validation(lib):
     # tile too long for any kernel
     rc = lib.tile_partition(fake, P(0x3000), None, None, 0, 1, 0, 64, None, fake, 1, 1 << 20, 0, ws, 256, None)
     assert rc == 2
-    # Theorem 2 partitions tiles of up to 16384 labels, the bitonic network 4096
+    # Theorem 2 and the bitonic network partition tiles of up to 16384 labels
     thm2, bitonic, naive = 2 << 8, 3 << 8, 15 << 8
     rc = lib.tile_partition(fake, P(0x3000), None, None, 0, 1, 0, 64, None, fake, 1, 16385, thm2, ws, 256, None)
     assert rc == 2

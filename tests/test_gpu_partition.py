@@ -152,9 +152,11 @@ def test_strided_payload_through_c_abi(ts, oracle):
     assert not got[:, 1:].any()          # the other words of each struct are untouched
 
 
+@pytest.mark.parametrize("schedule", ["thm2", "bitonic"])
 @pytest.mark.parametrize("cap", [8192, 16384])
-def test_thm2_wide_partition(ts, oracle, cap):
-    """Partition as the sorting of labels with Theorem 2 on 64 x 128 and 64 x 256 tiles."""
+def test_wide_partition_by_sort(ts, oracle, cap, schedule):
+    """Partition as the sorting of labels on 64 x 128 and 64 x 256 tiles: Theorem 2, and
+    the bitonic network spread over 2 and 4 wavefronts."""
     rng = np.random.default_rng(cap + 9)
     sizes = np.array([cap, cap - 1, 4097, 4096, 1, 0, cap // 2 + 3, cap])
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -162,7 +164,7 @@ def test_thm2_wide_partition(ts, oracle, cap):
     labels[: cap] = np.repeat(np.arange(64, dtype=np.uint32), cap // 64)   # exactly m copies
     labels[: cap] = rng.permutation(labels[: cap])
     payload = rng.standard_normal(off[-1]).astype(np.float32)
-    run_and_compare(ts, oracle, labels, payload, off, 64, "thm2", max_len=cap)
+    run_and_compare(ts, oracle, labels, payload, off, 64, schedule, max_len=cap)
 
 
 @pytest.mark.parametrize("schedule", ["thm2", "bitonic", "split"])
@@ -194,8 +196,6 @@ def test_payload_tiles_not_starting_at_zero(ts, oracle, schedule):
 def test_multichannel_payload(ts, oracle, schedule, cap):
     """Three channel-planar payload words per item: the first rides with the label, the
     others follow it through the source positions."""
-    if schedule == "bitonic" and cap > 4096:
-        pytest.skip("the bitonic schedule sorts tiles of up to 4096 keys")
     rng = np.random.default_rng(cap + 17)
     sizes = np.array([cap, cap - 1, 37, 0, cap // 2, cap])
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)

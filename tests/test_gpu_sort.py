@@ -213,7 +213,7 @@ def test_64bit_payload(ts, oracle, schedule):
     """A float64 payload (two 32-bit words per element, elem_stride 2) follows the sort."""
     from tests.gpu_util import dev
     rng = np.random.default_rng(77)
-    cap = 4096 if schedule == "bitonic" else 8192
+    cap = 8192
     sizes = np.array([cap, 1, 0, 3000, cap - 1, 700])
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     n = int(off[-1])
