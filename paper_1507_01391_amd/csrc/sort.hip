@@ -13,8 +13,8 @@
 //    (register-only, no memory traffic: the paper's row sort, Sec. 2); a row spread
 //    over H wavefronts is finished by compare-exchanges between wavefronts (each
 //    writes its registers to LDS and reads its partner's) and in-register merges;
-//  * direction masks: a row (or super-row) sorted descending is sorted ascending
-//    on complemented composites, which reverses their order;
+//  * direction masks (Theorem 2): a row (or super-row) sorted descending is sorted
+//    ascending on complemented composites, which reverses their order;
 //  * layout moves through LDS: each lane writes register c to the slot of its
 //    destination (lane L', register c') and then reads its new registers, one 32-bit
 //    plane of the composites at a time, with slots skewed so that every 32-lane
@@ -30,11 +30,12 @@
 // (64 items, one per row) lies inside one wavefront's columns, so the column sorts
 // need no exchange between wavefronts.
 //
-// BITONIC is Batcher's bitonic network on the 4096 items, with the stages on
-// register bits done in registers and the stages on lane bits done in registers
-// after a conflict-free transpose (the same transpose the column sort uses); tiles of
-// 8192 and 16384 keys spread the network over 2 and 4 wavefronts, whose stages on the
-// wavefront bits compare through LDS.
+// BITONIC is Batcher's bitonic network on the 4096 items in its mirror form (no
+// descending blocks, no masks), with the stages on register bits done in registers and
+// the stages on lane bits done in registers after a conflict-free transpose (the one the
+// column sort uses, with the lanes of half the rows reversed); tiles of 8192 and 16384
+// keys spread the network over 2 and 4 wavefronts, whose stages on the wavefront bits
+// compare through LDS.
 #include "bitonic.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
