@@ -319,9 +319,9 @@ ts_status ts_lds_probe(const uint32_t* lane_words, int op, int width, int iters,
    "permute_variant" -- router permute kernel for tiles of 4097..8192 items: 0: 16
       waves, persistent grid; 1: the same with registers capped for two workgroups per
       CU; 2: 8 waves; 6 (default) / 7: 16 capped waves, one workgroup per tile, with /
-      without streaming accesses; 8: 6 on a persistent grid; 9 / 10 / 11: 8 / 4 / 8
-      waves, one workgroup per tile, streaming accesses, registers for 4 / 2 / 3
-      waves per SIMD.
+      without streaming accesses; 8: 6 on a persistent grid; 9 / 10 / 11 / 12 / 13:
+      8 / 4 / 8 / 8 / 8 waves, one workgroup per tile, streaming accesses, registers
+      for 4 / 2 / 3 / 2 waves per SIMD / no register cap.
    "oneshot" -- launch shape of every other split-partition, split-sort and permute
       kernel: 1 (default) one workgroup per tile with streaming accesses, 0 a
       persistent grid.

@@ -35,7 +35,7 @@ KNOBS = {
     "merge_wide": ([32768, 16384, 8192, 4096], 32768),
     "oneshot": ([1, 0], 1),
     "partition_waves_4096": ([168, 176, 166, 164, 106, 108, 104], 168),
-    "permute_variant": ([6, 7, 8, 9, 10, 11, 1, 0, 2], 6),
+    "permute_variant": ([6, 7, 8, 9, 10, 11, 12, 13, 1, 0, 2], 6),
 }
 
 

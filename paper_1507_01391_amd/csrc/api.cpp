@@ -427,8 +427,8 @@ ts_status ts_tune(const char* knob, int value) {
         return TS_OK;
     }
     if (std::strcmp(knob, "permute_variant") == 0) {
-        if (!(value == 0 || value == 1 || value == 2 || (value >= 6 && value <= 11)))
-            return fail(TS_ERR_INVALID, "ts_tune: permute_variant must be one of 0, 1, 2, 6 .. 11");
+        if (!(value == 0 || value == 1 || value == 2 || (value >= 6 && value <= 13)))
+            return fail(TS_ERR_INVALID, "ts_tune: permute_variant must be one of 0, 1, 2, 6 .. 13");
         ts::set_permute_variant(value);
         return TS_OK;
     }

@@ -248,7 +248,8 @@ int64_t permute_split_capacity() { return 16384; }
 // (two workgroups per CU); 2 = 8 waves.  One workgroup per tile, 16 waves capped at 64
 // registers: 6 = streaming loads and stores (default), 7 = plain accesses; 8 = the
 // persistent form of 6; 9 = one workgroup of 8 waves per tile, streaming accesses; 10 =
-// 4 waves (32 columns each) and 11 = 8 waves with registers for three per SIMD, likewise.
+// 4 waves (32 columns each) and 11 = 8 waves with registers for three per SIMD, likewise;
+// 12 = 8 waves with registers for two per SIMD and 13 = 8 waves with no register cap.
 static int g_perm_variant = 6;
 void set_permute_variant(int v) { g_perm_variant = v; }
 
@@ -264,6 +265,8 @@ hipError_t launch_permute_split(const PermuteArgs& a, int64_t max_len, hipStream
         if (g_perm_variant == 9) return launch_perm<8, 8192, 4, true, true>(a, s);
         if (g_perm_variant == 10) return launch_perm<4, 8192, 2, true, true>(a, s);
         if (g_perm_variant == 11) return launch_perm<8, 8192, 3, true, true>(a, s);
+        if (g_perm_variant == 12) return launch_perm<8, 8192, 2, true, true>(a, s);
+        if (g_perm_variant == 13) return launch_perm<8, 8192, 0, true, true>(a, s);
         return launch_perm<16, 8192>(a, s);
     }
     return launch_perm_shaped<16, 16384>(a, s);

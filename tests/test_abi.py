@@ -133,7 +133,7 @@ def test_tune_knob_validation(lib):
     assert lib.ts_tune(b"sort_plan_16384", 4) == 0         # back to the default
     assert lib.ts_tune(b"merge_pack", 1) == 0
     for knob, bad, good in ((b"oneshot", 2, 1), (b"naive_oneshot", -1, 0), (b"sort_small_batch", -1, 1024),
-                            (b"permute_variant", 12, 6), (b"partition_waves_4096", 110, 168)):
+                            (b"permute_variant", 14, 6), (b"partition_waves_4096", 110, 168)):
         assert lib.ts_tune(knob, bad) == 1, knob
         assert lib.ts_tune(knob, good) == 0, knob
 

@@ -80,7 +80,7 @@ def test_validate_reports_non_permutation(ts, direction):
         ts.check_device_errors()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8, 9, 10, 11, 12, 13])
 @pytest.mark.parametrize("direction", ["scatter", "gather"])
 def test_permute_variants(ts, oracle, variant, direction):
     x, pi, _, off = inputs.permutation(seed=43, num_tiles=24, n=8192, family="uniform")
@@ -148,7 +148,7 @@ def test_multichannel_replay(ts, oracle, channels, direction, cap):
     run_and_compare(ts, oracle, x, pi, off, direction, max_len=cap)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("variant", [0, 1, 2, 6, 7, 8, 9, 10, 11, 12, 13])
 def test_multichannel_replay_variants(ts, oracle, variant):
     x, pi, _, off = inputs.permutation(seed=72, num_tiles=12, n=8192, family="transpose")
     x4 = np.stack([x, -x, 2 * x, x + 1]).astype(np.float32)
