@@ -54,6 +54,7 @@ int g_merge_wide = 32768;
 // wavefront; 4 .. 6 hold tiles of up to 8192 / 16384 / 32768 keys, one per workgroup of
 // 2 / 4 / 8 wavefronts.  Counter word of bin b (the piece list counts at word 4).
 constexpr int NUM_BINS = 7;
+constexpr int BIN_THREADS = 1024;  // threads (tiles) per workgroup of merge_bin_kernel
 TS_DEV int bin_counter(int b) { return b < 4 ? b : b + 1; }
 
 // Composite with PB position bits: slot << (32 + PB) | key << PB | pos.
@@ -99,12 +100,18 @@ TS_DEV void wave_append(uint32_t* counter, uint64_t* list, int64_t cap, uint32_t
 }
 
 
-__global__ __launch_bounds__(256) void merge_bin_kernel(MergeArgs a) {
+// One thread per tile.  The bin entries of a workgroup are counted in LDS first (one
+// LDS atomic per wave and bin) and reserved with one global atomic per workgroup and
+// bin: with a global atomic per wave the few bin counters serialised the launch.  The
+// tile loop steps by whole workgroups, so every wave of a workgroup meets the same
+// barriers.
+__global__ __launch_bounds__(BIN_THREADS) void merge_bin_kernel(MergeArgs a) {
+    __shared__ uint32_t wg_count[NUM_BINS], wg_base[NUM_BINS];
     const int lane = lane_id();
     const int64_t T = a.s.num_tiles;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); w0 < T; w0 += stride) {
-        const int64_t t = w0 + lane;
+    const int64_t stride = (int64_t)gridDim.x * BIN_THREADS;
+    for (int64_t b0 = (int64_t)blockIdx.x * BIN_THREADS; b0 < T; b0 += stride) {
+        const int64_t t = b0 + threadIdx.x;
         int64_t n = 0;
         bool bad = false;
         if (t < T) {
@@ -119,15 +126,23 @@ __global__ __launch_bounds__(256) void merge_bin_kernel(MergeArgs a) {
         int bin = -1;
         if (n > 0 && n <= K) bin = a.pack ? (n <= 512 ? 0 : n <= 1024 ? 1 : n <= 2048 ? 2 : 3) : 3;
         else if (n > K && n <= a.wide_max) bin = n <= 2 * K ? 4 : n <= 4 * K ? 5 : 6;
+        if (threadIdx.x < NUM_BINS) wg_count[threadIdx.x] = 0u;
+        __syncthreads();
+        uint32_t slot = 0;  // this tile's place among the workgroup's entries of its bin
         for (int b = 0; b < NUM_BINS; ++b) {
             const uint64_t m = ballot(bin == b);
             if (m == 0) continue;
             const int leader = __builtin_ctzll(m);
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&a.counters[bin_counter(b)], (uint32_t)popc64(m));
-            base = (uint32_t)__shfl((int)base, leader);
-            if (bin == b) a.bins[b * T + base + count_below(m)] = entry(t, 0);
+            uint32_t wb = 0;
+            if (lane == leader) wb = atomicAdd(&wg_count[b], (uint32_t)popc64(m));
+            wb = (uint32_t)__shfl((int)wb, leader);
+            if (bin == b) slot = wb + count_below(m);
         }
+        __syncthreads();
+        if (threadIdx.x < NUM_BINS && wg_count[threadIdx.x] > 0u)
+            wg_base[threadIdx.x] = atomicAdd(&a.counters[bin_counter((int)threadIdx.x)], wg_count[threadIdx.x]);
+        __syncthreads();
+        if (bin >= 0) a.bins[bin * T + wg_base[bin] + slot] = entry(t, 0);
         const uint32_t np = (n > a.wide_max) ? (uint32_t)((n + K - 1) / K) : 0u;
         wave_append(&a.counters[4], a.pieces, a.cap, a.s.err, np, t, lane);
         for (int r = 0; r < a.rounds; ++r) {
@@ -135,6 +150,7 @@ __global__ __launch_bounds__(256) void merge_bin_kernel(MergeArgs a) {
             wave_append(&a.counters[8 + r], a.round_lists + (int64_t)r * a.cap, a.cap, a.s.err, nr, t,
                         lane);
         }
+        __syncthreads();  // wg_count and wg_base are reused by the next group of tiles
     }
 }
 
@@ -544,9 +560,9 @@ hipError_t launch_sort_merge(const SortArgs& s, int64_t total_len, int64_t max_l
     hipError_t e = launch_fill_zero(a.counters, MERGE_COUNTER_BYTES, st);
     if (e != hipSuccess) return e;
     {
-        int64_t g = (s.num_tiles + 255) / 256;
-        if (g > 4096) g = 4096;
-        hipLaunchKernelGGL(merge_bin_kernel, dim3((unsigned)g), dim3(256), 0, st, a);
+        int64_t g = (s.num_tiles + BIN_THREADS - 1) / BIN_THREADS;
+        if (g > 1024) g = 1024;
+        hipLaunchKernelGGL(merge_bin_kernel, dim3((unsigned)g), dim3(BIN_THREADS), 0, st, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {
