@@ -63,19 +63,19 @@ MEASURED = {
            "lds_insts": 56623104, "lds_active": 163577856, "lds_conflicts": 0},
     "c3": {"profile": "profiles/permute_c3_counters.md",
            "sources": [KSRC + "permute.hip", KSRC + "route.hpp", KSRC + "common.hpp"],
-           "sha256_prefix": "2e5f6df73069899e", "knobs": {"permute_variant": 11},
-           "fetch": 919784 * 2 * 1024, "write": 1310850 * 1024,
+           "sha256_prefix": "123766577bea6a5e", "knobs": {"permute_variant": 13},
+           "fetch": 919786 * 2 * 1024, "write": 1310779 * 1024,
            "lds_insts": 35127296, "lds_active": 162529280, "lds_conflicts": 0},
     "c4": {"profile": "profiles/merge_c4_counters.md",
            "sources": [KSRC + "merge.hip", KSRC + "bitonic.hpp", KSRC + "common.hpp"],
-           "sha256_prefix": "967d1d22f957b980", "knobs": {"merge_wide": 32768},
-           "fetch": 2724705 * 2 * 1024, "write": 7895876 * 1024,
-           "lds_insts": 850484778, "lds_active": 2530114548, "lds_conflicts": 0},
+           "sha256_prefix": "fe32bc9ad782c742", "knobs": {"merge_wide": 32768},
+           "fetch": 2729913 * 2 * 1024, "write": 7895657 * 1024,
+           "lds_insts": 850497616, "lds_active": 2530140294, "lds_conflicts": 0},
     "c5": {"profile": "profiles/sort_payload_c5_counters.md",
            "sources": [KSRC + "sort.hip", KSRC + "bitonic.hpp", KSRC + "permute.hip", KSRC + "route.hpp",
                        KSRC + "common.hpp", KSRC + "api.cpp", "paper_1507_01391_amd/autograd.py"],
-           "sha256_prefix": "45acfa99e6fd7a7e", "knobs": {"sort_plan_16384": 3, "oneshot": 1},
-           "fetch": 2682067 * 2 * 1024, "write": 5161059 * 1024,
+           "sha256_prefix": "c2239d90cbfce7c3", "knobs": {"sort_plan_16384": 3, "oneshot": 1},
+           "fetch": 2676560 * 2 * 1024, "write": 5162766 * 1024,
            "lds_insts": 180387840, "lds_active": 786300928, "lds_conflicts": 0},
 }
 
