@@ -151,6 +151,17 @@ def test_merge_long_tile_up_to_limit(ts, oracle):
     run_and_compare(ts, oracle, keys, None, off, "merge", max_len=1 << 20)
 
 
+def test_merge_more_tiles_than_one_binning_pass(ts, oracle):
+    """1.1 million tiles of 0..5 keys: the binning kernel covers 1024 x 1024 tiles per
+    pass, so this batch takes two passes of its tile loop."""
+    rng = np.random.default_rng(123)
+    sizes = rng.integers(0, 6, size=1_100_000)
+    sizes[-3:] = [4096, 5000, 1]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    keys = rng.integers(0, 2**32, size=int(off[-1]), dtype=np.uint32)
+    run_and_compare(ts, oracle, keys, None, off, "merge", max_len=8192)
+
+
 def test_merge_skips_tiles_outside_the_arrays(ts):
     from tests.gpu_util import dev
     keys = np.arange(4000, dtype=np.uint32)[::-1].copy()
