@@ -88,11 +88,6 @@ __constant__ Phase kThm2[13] = {
     {0, 0, MOVE_T},                              // final row sort; to store order
 };
 
-// Payload of the ranks a lane holds, gathered from the input at each rank's source
-// position (a global gather inside the tile, no LDS): register c of lane L holds rank
-// rank_of(c), whose source position is pos[c].  Used where no permutation is kept for a
-// second, routed launch (partition through a sort schedule).  Addresses are rebuilt per
-// channel from an opaque lane index, so none stay live across the channel loop.
 // Stores of keys and positions: register c of lane L holds rank rb + 64 c + L, valid
 // below n.  Buffer resources over the ranks rb ..: a column is the lane offset plus an
 // immediate, and stores of ranks >= n are dropped by the hardware range check, so
@@ -118,6 +113,11 @@ TS_DEV void store_sorted(const SortArgs& a, int64_t o, int rb, int n, const uint
     }
 }
 
+// Payload of the ranks a lane holds, gathered from the input at each rank's source
+// position (a global gather inside the tile, no LDS): register c of lane L holds rank
+// rank_of(c), whose source position is pos[c].  Used where no permutation is kept for a
+// second, routed launch (partition through a sort schedule).  Addresses are rebuilt per
+// channel from an opaque lane index, so none stay live across the channel loop.
 template <int NREG, typename RankFn>
 TS_DEV void gather_payload(const SortArgs& a, int64_t o, int n, const uint32_t (&pos)[NREG], int lane,
                            RankFn rank_of) {
