@@ -110,7 +110,9 @@ def test_wide_exchange_slots(H):
 
 # ---- data flow of the whole kernel ---------------------------------------------------
 
-FULL = np.uint64(0xFFFFFFFFFFFFFFFF)
+# composites are key << 30 | position, below 2^62; xor with 2^62 - 1 reverses the order
+FULL = np.uint64((1 << 62) - 1)
+POS_MASK = np.uint64((1 << 30) - 1)
 
 
 def mask_of(kind):
@@ -210,7 +212,7 @@ def run_wide_kernel(keys, H):
         for c in range(64):
             i = 64 * (64 * h + c) + LANES
             k = np.where(i < n, keys[np.minimum(i, max(n - 1, 0))] if n else 0, 0xFFFFFFFF)
-            V[h, :, c] = (k.astype(np.uint64) << np.uint64(32)) | i.astype(np.uint64)
+            V[h, :, c] = (k.astype(np.uint64) << np.uint64(30)) | i.astype(np.uint64)
     for pre, post, sort, move in PHASES:
         V = V ^ mask_of(pre)[None, :, None]
         V = wide_row_sort(V, H) if sort == "row" else row_sort_regs(V)
@@ -230,8 +232,8 @@ def test_wide_kernel_data_flow_sorts(H, n, seed, hi):
     keys = rng.integers(0, hi, size=n, dtype=np.uint64).astype(np.uint32)
     out = run_wide_kernel(keys, H)
     order = np.argsort(keys, kind="stable")
-    assert np.array_equal((out >> np.uint64(32)).astype(np.uint32), keys[order])
-    assert np.array_equal((out & np.uint64(0xFFFFFFFF)).astype(np.int64), order)
+    assert np.array_equal((out >> np.uint64(30)).astype(np.uint32), keys[order])
+    assert np.array_equal((out & POS_MASK).astype(np.int64), order)
 
 
 def test_wide_kernel_data_flow_01_inputs():
@@ -241,7 +243,7 @@ def test_wide_kernel_data_flow_01_inputs():
         for _ in range(3):
             keys = (rng.random(64 * 64 * H) < rng.random()).astype(np.uint32)
             out = run_wide_kernel(keys, H)
-            assert np.array_equal((out & np.uint64(0xFFFFFFFF)).astype(np.int64),
+            assert np.array_equal((out & POS_MASK).astype(np.int64),
                                   np.argsort(keys, kind="stable"))
 
 
