@@ -74,7 +74,7 @@ MEASURED = {
     "c5": {"profile": "profiles/sort_payload_c5_counters.md",
            "sources": [KSRC + "sort.hip", KSRC + "bitonic.hpp", KSRC + "permute.hip", KSRC + "route.hpp",
                        KSRC + "common.hpp", KSRC + "api.cpp", "paper_1507_01391_amd/autograd.py"],
-           "sha256_prefix": "a236933e4d56d7a9", "knobs": {"sort_plan_16384": 3, "oneshot": 1},
+           "sha256_prefix": "3f5a07aead9d6874", "knobs": {"sort_plan_16384": 3, "oneshot": 1},
            "fetch": 2676560 * 2 * 1024, "write": 5162766 * 1024,
            "lds_insts": 180387840, "lds_active": 786300928, "lds_conflicts": 0},
 }

@@ -53,11 +53,41 @@ TS_DEV uint32_t comp_key(uint64_t c) { return (uint32_t)(c >> SORT_POS_BITS); }
 TS_DEV uint32_t comp_pos(uint64_t c) { return (uint32_t)c & ((1u << SORT_POS_BITS) - 1u); }
 
 // One phase of a schedule: xor with `pre`, row sort, xor with `post`, then a layout
-// move.
+// move.  `runs` (see row_sort_from): 1 when every row enters the phase as runs sorted
+// in alternating directions (rows sorted in alternating directions, then moved from
+// row-major to column-major order inside their super-row), 2 when every column does
+// (the column sort after the second such Lemma 1); 0 otherwise.
 struct Phase {
     uint8_t pre, post;   // mask kinds, see mask_of
     uint8_t move;        // Move
+    uint8_t runs;
 };
+
+// The register row sort from bitonic level `start` on (2 = the whole network).  Where a
+// phase's rows arrive as runs of r items sorted in alternating directions, every block
+// of 2r registers is already bitonic and levels 2 .. r are skipped: r = 8 for the
+// 64 x 64 tile and for the column sorts, r = 8H for a row of a 64 x 64H tile (each
+// wavefront's part holds runs of 8H items of 8 source rows).  `start` is wave-uniform,
+// so each level is one scalar branch and the network's code appears once.
+template <int K>
+TS_DEV void sort_level(uint64_t (&v)[R]) { net_stages<(K < R ? K : 0), K / 2>(v); }
+TS_DEV void row_sort_from(uint64_t (&v)[R], int start) {
+    if (start <= 2) sort_level<2>(v);
+    __builtin_amdgcn_sched_barrier(0);
+    if (start <= 4) sort_level<4>(v);
+    __builtin_amdgcn_sched_barrier(0);
+    if (start <= 8) sort_level<8>(v);
+    __builtin_amdgcn_sched_barrier(0);
+    if (start <= 16) sort_level<16>(v);
+    __builtin_amdgcn_sched_barrier(0);
+    if (start <= 32) sort_level<32>(v);
+    __builtin_amdgcn_sched_barrier(0);
+    sort_level<64>(v);
+}
+TS_DEV int runs_start(int runs, int H) {
+    const int r = runs == 1 ? 8 * H : 8;
+    return runs == 0 ? 2 : (2 * r < 64 ? 2 * r : 64);
+}
 
 // Mask kinds: 0 none; 1 odd lanes (alternating rows); 2 odd super-rows (lanes 8..15,
 // 24..31, ...); 3 both; 8 + kb: lanes with bit kb set (bitonic direction).
@@ -75,17 +105,17 @@ TS_DEV uint64_t mask_of(int kind, int lane) {
 __constant__ Phase kThm2[13] = {
     // Lemma 1 on every super-row, ascending: alternate-direction row sort + RM->CM,
     // ascending row sort + CM->RM, twice
-    {1, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},
-    {1, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},
-    {0, 0, MOVE_T},                              // ascending row sort; column sort starts
-    {0, 0, MOVE_T},                              // column sort: sort, transpose back
+    {1, 1, MOVE_RM2CM, 0}, {0, 0, MOVE_CM2RM, 1},
+    {1, 1, MOVE_RM2CM, 0}, {0, 0, MOVE_CM2RM, 1},
+    {0, 0, MOVE_T, 0},                           // ascending row sort; column sort starts
+    {0, 0, MOVE_T, 0},                           // column sort: sort, transpose back
     // Lemma 1 again, odd super-rows descending: their values stay complemented from
     // the first pre-mask (3 = super-row ^ alternation) to the last post-mask (2)
-    {3, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},
-    {1, 1, MOVE_RM2CM}, {0, 0, MOVE_CM2RM},
-    {0, 2, MOVE_T},                              // ascending row sort; column sort starts
-    {0, 0, MOVE_T},                              // column sort: sort, transpose back
-    {0, 0, MOVE_T},                              // final row sort; to store order
+    {3, 1, MOVE_RM2CM, 0}, {0, 0, MOVE_CM2RM, 1},
+    {1, 1, MOVE_RM2CM, 0}, {0, 0, MOVE_CM2RM, 1},
+    {0, 2, MOVE_T, 0},                           // ascending row sort; column sort starts
+    {0, 0, MOVE_T, 2},                           // column sort: sort, transpose back
+    {0, 0, MOVE_T, 0},                           // final row sort; to store order
 };
 
 // Stores of keys and positions: register c of lane L holds rank rb + 64 c + L, valid
@@ -185,7 +215,7 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
             for (int p = 0; p < 13; ++p) {
                 const Phase ph = kThm2[p];
                 xor_all(v, mask_of(ph.pre, lane));
-                row_sort(v);
+                row_sort_from(v, runs_start(ph.runs, 1));
                 xor_all(v, mask_of(ph.post, lane));
                 layout_move(A, v, ph.move, lane);
             }
@@ -212,20 +242,20 @@ void sort4096_kernel(SortArgs a, const int64_t* __restrict__ offs) {
 enum WideSort : uint8_t { SORT_ROW = 0, SORT_COL = 1 };
 enum WideMove : uint8_t { WM_RM2CM = 0, WM_CM2RM = 1, WM_T = 2, WM_FINAL = 3 };
 struct WidePhase {
-    uint8_t pre, post, sort, move;
+    uint8_t pre, post, sort, move, runs;
 };
 
 // The 13 row sorts of the Theorem 2 schedule, as in kThm2; the two column sorts sort
 // 64-item columns after an in-wavefront transpose, and the last move puts the tile in
 // store order.
 __constant__ WidePhase kThm2Wide[13] = {
-    {1, 1, SORT_ROW, WM_RM2CM}, {0, 0, SORT_ROW, WM_CM2RM},
-    {1, 1, SORT_ROW, WM_RM2CM}, {0, 0, SORT_ROW, WM_CM2RM},
-    {0, 0, SORT_ROW, WM_T},     {0, 0, SORT_COL, WM_T},
-    {3, 1, SORT_ROW, WM_RM2CM}, {0, 0, SORT_ROW, WM_CM2RM},
-    {1, 1, SORT_ROW, WM_RM2CM}, {0, 0, SORT_ROW, WM_CM2RM},
-    {0, 2, SORT_ROW, WM_T},     {0, 0, SORT_COL, WM_T},
-    {0, 0, SORT_ROW, WM_FINAL},
+    {1, 1, SORT_ROW, WM_RM2CM, 0}, {0, 0, SORT_ROW, WM_CM2RM, 1},
+    {1, 1, SORT_ROW, WM_RM2CM, 0}, {0, 0, SORT_ROW, WM_CM2RM, 1},
+    {0, 0, SORT_ROW, WM_T, 0},     {0, 0, SORT_COL, WM_T, 0},
+    {3, 1, SORT_ROW, WM_RM2CM, 0}, {0, 0, SORT_ROW, WM_CM2RM, 1},
+    {1, 1, SORT_ROW, WM_RM2CM, 0}, {0, 0, SORT_ROW, WM_CM2RM, 1},
+    {0, 2, SORT_ROW, WM_T, 0},     {0, 0, SORT_COL, WM_T, 2},
+    {0, 0, SORT_ROW, WM_FINAL, 0},
 };
 
 // LDS words of the wide kernel: the largest of the cross-wavefront moves (one 32-bit
@@ -370,7 +400,7 @@ void thm2_wide_kernel(SortArgs a, const int64_t* __restrict__ offs) {
             const bool row = ph.sort == SORT_ROW;
             const uint64_t m1 = (row && (h & 1)) ? COMP_MASK : 0ull;
             xor_all(v, mask_of(ph.pre, lane) ^ m1);
-            row_sort(v);
+            row_sort_from(v, runs_start(ph.runs, H));
             xor_all(v, m1);
             if (row) wide_row_merge<H>(X, v, h, lane);
             xor_all(v, mask_of(ph.post, lane));

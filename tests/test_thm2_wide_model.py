@@ -256,3 +256,148 @@ def test_wide_exchange_slots_fit_the_transpose_arrays():
     for H in (2, 4, 8):
         top = 2 * ((XCH * (H - 1) + XCH - 1) * 64 + 63) + 1
         assert top < H * MOVE_WORDS
+
+
+# ---- row sorts that skip levels on runs (the phase table's `runs` field) ------------------
+
+RUNS = [0, 1, 0, 1, 0, 0, 0, 1, 0, 1, 0, 2, 0]   # per phase, as in both kernels' tables
+
+
+def runs_start(runs, H):
+    r = 8 * H if runs == 1 else 8
+    return 2 if runs == 0 else min(2 * r, 64)
+
+
+def network_from(v, start):
+    """The kernels' register bitonic network from level `start` on (last axis, 64 items):
+    level K sorts K-blocks, ascending where bit K of the index is clear (K = 64: all)."""
+    idx = np.arange(64)
+    K = start
+    while K <= 64:
+        j = K // 2
+        while j >= 1:
+            lo = idx[(idx & j) == 0]
+            hi = lo | j
+            asc = ((lo & K) == 0) if K < 64 else np.ones(lo.shape, bool)
+            a, b = v[..., lo].copy(), v[..., hi].copy()
+            mn, mx = np.minimum(a, b), np.maximum(a, b)
+            v[..., lo] = np.where(asc, mn, mx)
+            v[..., hi] = np.where(asc, mx, mn)
+            j //= 2
+        K *= 2
+    return v
+
+
+def run_kernel_with_skips(keys, H):
+    """The Theorem 2 data flow with every register row sort started at the phase's level
+    (64 x 64H tile; H = 1 is the one-wavefront kernel, whose rows need no exchange)."""
+    n = len(keys)
+    M = 64 * H
+    V = np.empty((H, 64, 64), dtype=np.uint64)
+    for h in range(H):
+        for c in range(64):
+            i = 64 * (64 * h + c) + LANES
+            k = np.where(i < n, keys[np.minimum(i, max(n - 1, 0))] if n else 0, 0xFFFFFFFF)
+            V[h, :, c] = (k.astype(np.uint64) << np.uint64(30)) | i.astype(np.uint64)
+    for p, (pre, post, sort, move) in enumerate(PHASES):
+        V = V ^ mask_of(pre)[None, :, None]
+        start = runs_start(RUNS[p], H)
+        if sort == "row":
+            for h in range(H):
+                m1 = FULL if h & 1 else np.uint64(0)
+                V[h] = network_from(V[h] ^ m1, start) ^ m1
+            if H > 1:
+                # the exchanges and in-register merges of wide_row_sort after the own sort
+                W = V.copy()
+                asc128 = (lambda h: True) if H == 2 else (lambda h: ((h >> 1) & 1) == 0)
+                for h in range(H):
+                    hp = h ^ 1
+                    keep_min = (h < hp) == asc128(h)
+                    W[h] = np.minimum(V[h], V[hp]) if keep_min else np.maximum(V[h], V[hp])
+                V = W
+                for h in range(H):
+                    m2 = np.uint64(0) if asc128(h) else FULL
+                    V[h] = bitonic_merge_regs(V[h] ^ m2) ^ m2
+                if H == 4:
+                    for bit in (2, 1):
+                        W = V.copy()
+                        for h in range(H):
+                            hp = h ^ bit
+                            W[h] = np.minimum(V[h], V[hp]) if h < hp else np.maximum(V[h], V[hp])
+                        V = W
+                    for h in range(H):
+                        V[h] = bitonic_merge_regs(V[h])
+        else:
+            V = network_from(V, start)
+        V = V ^ mask_of(post)[None, :, None]
+        V = transpose_in_wave(V) if move == "T" else cross_move(V, H, move)
+    out = np.empty(64 * M, dtype=np.uint64)
+    for h in range(H):
+        for c in range(64):
+            out[64 * (64 * h + c) + LANES] = V[h, :, c]
+    return out[:n]
+
+
+@pytest.mark.parametrize("H", [1, 2, 4])
+@pytest.mark.parametrize("seed,hi", [(1, 2**32), (2, 3), (3, 1)])
+def test_row_sorts_started_at_the_runs_level_still_sort(H, seed, hi):
+    """Phases 1, 3, 7, 9 see every row (each wavefront's part of it) as runs of 8H items in
+    alternating directions, phase 11 every column as runs of 8: starting the register
+    network at level 2r there still sorts the tile (full tiles, ties, all-equal keys)."""
+    rng = np.random.default_rng(seed * 10 + H)
+    n = 4096 * H
+    keys = rng.integers(0, hi, size=n, dtype=np.uint64).astype(np.uint32)
+    out = run_kernel_with_skips(keys, H)
+    assert np.array_equal((out & POS_MASK).astype(np.int64), np.argsort(keys, kind="stable"))
+
+
+def test_row_sorts_started_at_the_runs_level_ragged():
+    rng = np.random.default_rng(17)
+    for H, n in ((1, 3000), (2, 5000), (4, 9999), (4, 64)):
+        keys = rng.integers(0, 7, size=n, dtype=np.uint64).astype(np.uint32)
+        out = run_kernel_with_skips(keys, H)
+        assert np.array_equal((out & POS_MASK).astype(np.int64), np.argsort(keys, kind="stable"))
+
+
+def bitonic_blocks(row, size):
+    """Every block of `size` items is strictly ascending then descending, or the reverse,
+    with the turn in the middle (two sorted runs of size / 2 in opposite directions)."""
+    half = size // 2
+    for b in range(0, len(row), size):
+        x = np.diff(row[b:b + half].astype(object))
+        y = np.diff(row[b + half:b + size].astype(object))
+        up_x, dn_x = all(t > 0 for t in x), all(t < 0 for t in x)
+        up_y, dn_y = all(t > 0 for t in y), all(t < 0 for t in y)
+        if not ((up_x and dn_y) or (dn_x and up_y)):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("H", [1, 2, 4])
+def test_phase_inputs_are_runs_where_the_table_says(H):
+    """The property the kernels rely on, checked directly: at every phase whose `runs` is
+    set, the register row each wavefront sorts (after the phase's masks) consists of
+    blocks of 2r items that are bitonic (r = 8H after the super-row moves, 8 for the
+    column sort), so the network may start at level 2r."""
+    rng = np.random.default_rng(23 + H)
+    n = 4096 * H
+    keys = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+    V = np.empty((H, 64, 64), dtype=np.uint64)
+    for h in range(H):
+        for c in range(64):
+            i = 64 * (64 * h + c) + LANES
+            V[h, :, c] = (keys[i].astype(np.uint64) << np.uint64(30)) | i.astype(np.uint64)
+    for p, (pre, post, sort, move) in enumerate(PHASES):
+        V = V ^ mask_of(pre)[None, :, None]
+        if RUNS[p]:
+            size = runs_start(RUNS[p], H)
+            for h in range(H):
+                m1 = FULL if (sort == "row" and h & 1) else np.uint64(0)
+                W = V[h] ^ m1
+                assert all(bitonic_blocks(W[L], size) for L in range(64)), (p, h)
+        if sort == "row":
+            V = wide_row_sort(V, H) if H > 1 else row_sort_regs(V)
+        else:
+            V = row_sort_regs(V)
+        V = V ^ mask_of(post)[None, :, None]
+        V = transpose_in_wave(V) if move == "T" else cross_move(V, H, move)
