@@ -289,15 +289,20 @@ def test_thm2_wide_distributions(ts, oracle, cap):
     run_and_compare(ts, oracle, keys, payload, off, "thm2", max_len=cap)
 
 
+@pytest.mark.parametrize("schedule", ["thm2", "bitonic"])
 @pytest.mark.parametrize("cap", [8192, 16384])
-def test_thm2_wide_f32_and_edges(ts, oracle, cap):
+def test_thm2_wide_f32_and_edges(ts, oracle, cap, schedule):
+    """fp32 keys with the special values and ragged lengths around the wavefront
+    boundaries, on the schedules spread over 2 and 4 wavefronts."""
     rng = np.random.default_rng(cap + 4)
     sizes = [0, 1, 2, 63, 64, 65, 4095, 4096, 4097, cap // 2, cap - 64, cap - 1, cap]
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     x = rng.standard_normal(int(off[-1])).astype(np.float32)
     x[:8] = np.array([-np.inf, np.inf, -0.0, 0.0, 1e-40, -1e-40, 3.0, -3.0], np.float32)
+    x[8:10] = np.array([0x7FC00001, 0xFFC00002], np.uint32).view(np.float32)   # NaNs, by their bits
     rng.shuffle(x)
-    run_and_compare(ts, oracle, x.view(np.uint32), None, off, "thm2", max_len=cap, f32=True)
+    payload = rng.integers(0, 2**32, size=int(off[-1]), dtype=np.uint32)
+    run_and_compare(ts, oracle, x.view(np.uint32), payload, off, schedule, max_len=cap, f32=True)
 
 
 # Keys at the edges of the range the sorting networks compare composites in, read as
