@@ -194,29 +194,16 @@ def bench_c2(args, torch, ts, inputs):
         ts.tile_partition(d_lab, d_pay, d_off, num_classes=64, max_tile_len=4096,
                           labels_out=lab_out, payload_out=pay_out)
 
-    log("[bench] timing the conflict-free partition ...")
-    wall_ms, mean_ms, _ = timed_launches(step, args.steps, args.warmup, torch)
-    ts.check_device_errors()
-    ms_per_step = wall_ms / args.steps
-    value = n_total / (ms_per_step / 1e3)
-    rec = measured("c2", ts) if T == 65536 else None
-    roof = roofline(PARTITION_BYTES_PER_KEY, n_total, mean_ms, rec, PARTITION_LDS_BYTES_PER_KEY)
-
-    # parity on sampled tiles (oracle computes them one by one)
     from oracle import oracle as orc
-    rng = np.random.default_rng(0)
-    sample = np.sort(rng.choice(T, size=min(16, T), replace=False))
-    lo = lab_out.cpu().numpy().view(np.uint32)
-    po = pay_out.cpu().numpy().view(np.uint32)
-    ok = True
-    for t in sample:
-        a, b = int(offsets[t]), int(offsets[t + 1])
-        wl, wp, _ = orc.tile_partition(labels[a:b], payload[a:b].view(np.uint32), num_classes=64)
-        ok &= bool(np.array_equal(lo[a:b], wl) and np.array_equal(po[a:b], wp))
-    if not ok:
-        log("[bench] PARITY FAILURE on sampled tiles")
-
-    extra = {"parity_sampled_tiles": f"{len(sample)} tiles bit-exact" if ok else "MISMATCH"}
+    extra = {}
+    if not args.no_extra:
+        # The same timing first, in a process whose GPU has been idle: the clocks are
+        # still ramping, and this figure is reported beside the headline, which is timed
+        # after the other workloads below have brought the GPU to its steady clock.
+        log("[bench] timing the conflict-free partition, first in the process ...")
+        w0, m0, _ = timed_launches(step, args.steps, args.warmup, torch)
+        extra["c2_first_in_process_ms_per_step"] = w0 / args.steps
+        extra["c2_first_in_process_kernel_mean_ms"] = m0
     if not args.no_extra:
         def naive():
             ts.tile_partition(d_lab, d_pay, d_off, num_classes=64, max_tile_len=4096,
@@ -260,6 +247,28 @@ def bench_c2(args, torch, ts, inputs):
         extra["c4_segmented_sort"] = bench_c4(args, torch, ts, inputs, orc)
         extra["c5_sort_with_payload"] = bench_c5(args, torch, ts, inputs, orc)
         extra.update(bench_device_sort(torch, ts))
+
+    log("[bench] timing the conflict-free partition ...")
+    wall_ms, mean_ms, _ = timed_launches(step, args.steps, args.warmup, torch)
+    ts.check_device_errors()
+    ms_per_step = wall_ms / args.steps
+    value = n_total / (ms_per_step / 1e3)
+    rec = measured("c2", ts) if T == 65536 else None
+    roof = roofline(PARTITION_BYTES_PER_KEY, n_total, mean_ms, rec, PARTITION_LDS_BYTES_PER_KEY)
+
+    # parity on sampled tiles of the timed run's output (the oracle computes them one by one)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(T, size=min(16, T), replace=False))
+    lo = lab_out.cpu().numpy().view(np.uint32)
+    po = pay_out.cpu().numpy().view(np.uint32)
+    ok = True
+    for t in sample:
+        a, b = int(offsets[t]), int(offsets[t + 1])
+        wl, wp, _ = orc.tile_partition(labels[a:b], payload[a:b].view(np.uint32), num_classes=64)
+        ok &= bool(np.array_equal(lo[a:b], wl) and np.array_equal(po[a:b], wp))
+    if not ok:
+        log("[bench] PARITY FAILURE on sampled tiles")
+    extra["parity_sampled_tiles"] = f"{len(sample)} tiles bit-exact" if ok else "MISMATCH"
 
     cpu = None
     if not args.no_cpu:
